@@ -1,0 +1,200 @@
+"""numpy front end of the CPU oracle (``sgm_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU-baseline
+leg of the benchmark may import this module; the GPU library never does.  It
+shares no code with the GPU path: the C file is compiled here with the host
+compiler into its own shared object.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import subprocess
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sgm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+                               "-fno-fast-math", "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        _lib = ct.CDLL(_LIB)
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ct.c_void_p)
+
+
+class OrcParams(ct.Structure):
+    _fields_ = [(n, ct.c_int32) for n in (
+        "width", "height", "max_disp", "census_w", "census_h", "census_mode", "p1", "p2",
+        "uniqueness_pct", "lr_max_diff", "num_paths", "median", "subpixel")] + [
+        ("focal_px", ct.c_float), ("baseline_m", ct.c_float)]
+
+
+class OrcResult(ct.Structure):
+    _fields_ = [("census_l", ct.c_void_p), ("census_r", ct.c_void_p), ("S", ct.c_void_p),
+                ("dint", ct.c_void_p), ("s1", ct.c_void_p), ("s2", ct.c_void_p),
+                ("dright", ct.c_void_p), ("flags", ct.c_void_p), ("dsub", ct.c_void_p),
+                ("disp", ct.c_void_p), ("depth", ct.c_void_p)]
+
+
+FLAG_UNIQUE, FLAG_LR, FLAG_NONZERO, FLAG_FINAL = 1, 2, 4, 8
+
+
+def ir_noise(img: np.ndarray, gamma: np.ndarray, n: np.ndarray) -> np.ndarray:
+    img = np.ascontiguousarray(img, np.uint8)
+    gamma = np.ascontiguousarray(gamma, np.float32)
+    n = np.ascontiguousarray(n, np.float32)
+    out = np.empty_like(img)
+    lib().orc_ir_noise(_p(img), _p(gamma), _p(n), _p(out), ct.c_int64(img.size))
+    return out
+
+
+def census_bits(cw: int, ch: int, mode: int) -> int:
+    return int(lib().orc_census_bits(cw, ch, mode))
+
+
+def census(img: np.ndarray, cw: int = 7, ch: int = 9, mode: int = 0) -> np.ndarray:
+    img = np.ascontiguousarray(img, np.uint8)
+    H, W = img.shape
+    out = np.empty((H, W), np.uint64)
+    lib().orc_census(_p(img), W, H, W, cw, ch, mode, _p(out))
+    return out
+
+
+def popcount(v: int) -> int:
+    return int(lib().orc_popcount(ct.c_uint64(int(v))))
+
+
+def cost(cl: np.ndarray, cr: np.ndarray, D: int, bits: int) -> np.ndarray:
+    cl = np.ascontiguousarray(cl, np.uint64)
+    cr = np.ascontiguousarray(cr, np.uint64)
+    H, W = cl.shape
+    C = np.empty((H, W, D), np.uint8)
+    lib().orc_cost(_p(cl), _p(cr), W, H, D, bits, _p(C))
+    return C
+
+
+def path(C: np.ndarray, dx: int, dy: int, p1: int, p2: int) -> np.ndarray:
+    C = np.ascontiguousarray(C, np.uint8)
+    H, W, D = C.shape
+    L = np.empty((H, W, D), np.uint16)
+    lib().orc_path(_p(C), W, H, D, dx, dy, p1, p2, _p(L))
+    return L
+
+
+def path_dirs(num_paths: int):
+    out = []
+    for i in range(num_paths):
+        dx, dy = ct.c_int(), ct.c_int()
+        lib().orc_path_dir(i, ct.byref(dx), ct.byref(dy))
+        out.append((dx.value, dy.value))
+    return out
+
+
+def aggregate(C: np.ndarray, num_paths: int, p1: int, p2: int) -> np.ndarray:
+    C = np.ascontiguousarray(C, np.uint8)
+    H, W, D = C.shape
+    S = np.empty((H, W, D), np.uint32)
+    lib().orc_aggregate(_p(C), W, H, D, num_paths, p1, p2, _p(S))
+    return S
+
+
+def wta(S: np.ndarray, uniqueness_pct: int, subpixel: int = 1):
+    S = np.ascontiguousarray(S, np.uint32)
+    H, W, D = S.shape
+    dint = np.empty((H, W), np.int32)
+    s1 = np.empty((H, W), np.int32)
+    s2 = np.empty((H, W), np.int32)
+    vu = np.empty((H, W), np.uint8)
+    dsub = np.empty((H, W), np.float64)
+    lib().orc_wta(_p(S), W, H, D, uniqueness_pct, subpixel, _p(dint), _p(s1), _p(s2), _p(vu), _p(dsub))
+    return dint, s1, s2, vu, dsub
+
+
+def right_disp(S: np.ndarray) -> np.ndarray:
+    S = np.ascontiguousarray(S, np.uint32)
+    H, W, D = S.shape
+    dR = np.empty((H, W), np.int32)
+    lib().orc_right_disp(_p(S), W, H, D, _p(dR))
+    return dR
+
+
+def lr_check(dint: np.ndarray, dR: np.ndarray, lr: int) -> np.ndarray:
+    dint = np.ascontiguousarray(dint, np.int32)
+    dR = np.ascontiguousarray(dR, np.int32)
+    H, W = dint.shape
+    out = np.empty((H, W), np.uint8)
+    lib().orc_lr_check(_p(dint), _p(dR), W, H, lr, _p(out))
+    return out
+
+
+def median3(a: np.ndarray) -> np.ndarray:
+    a = np.ascontiguousarray(a, np.float64)
+    H, W = a.shape
+    out = np.empty_like(a)
+    lib().orc_median3(_p(a), W, H, _p(out))
+    return out
+
+
+def depth(disp: np.ndarray, focal_px: float, baseline_m: float) -> np.ndarray:
+    disp = np.ascontiguousarray(disp, np.float64)
+    out = np.empty_like(disp)
+    lib().orc_depth(_p(disp), ct.c_int64(disp.size), ct.c_double(focal_px), ct.c_double(baseline_m),
+                    _p(out))
+    return out
+
+
+@dataclass
+class SGMResult:
+    census_l: np.ndarray
+    census_r: np.ndarray
+    S: Optional[np.ndarray]
+    dint: np.ndarray
+    s1: np.ndarray
+    s2: np.ndarray
+    dright: np.ndarray
+    flags: np.ndarray
+    dsub: np.ndarray
+    disp: np.ndarray
+    depth: np.ndarray
+
+
+def sgm(params: dict, left: np.ndarray, right: np.ndarray, keep_volume: bool = False) -> SGMResult:
+    """The whole depth path on an already-noised pair; ``params`` as the GPU library's."""
+    left = np.ascontiguousarray(left, np.uint8)
+    right = np.ascontiguousarray(right, np.uint8)
+    H, W = left.shape
+    assert params["width"] == W and params["height"] == H
+    D = params["max_disp"]
+    pp = OrcParams(**{k: params[k] for k, _ in OrcParams._fields_})
+    arrs = dict(census_l=np.empty((H, W), np.uint64), census_r=np.empty((H, W), np.uint64),
+                S=np.empty((H, W, D), np.uint32) if keep_volume else None,
+                dint=np.empty((H, W), np.int32), s1=np.empty((H, W), np.int32),
+                s2=np.empty((H, W), np.int32), dright=np.empty((H, W), np.int32),
+                flags=np.empty((H, W), np.uint8), dsub=np.empty((H, W), np.float64),
+                disp=np.empty((H, W), np.float64), depth=np.empty((H, W), np.float64))
+    res = OrcResult(**{k: (None if v is None else v.ctypes.data) for k, v in arrs.items()})
+    rc = lib().orc_sgm(ct.byref(pp), _p(left), _p(right), ct.byref(res))
+    if rc != 0:
+        raise MemoryError("oracle allocation failed")
+    return SGMResult(**arrs)
