@@ -1,0 +1,360 @@
+// C ABI of the depth library: parameter validation, the handle and its device
+// scratch, and the order in which the passes are enqueued.
+#include <new>
+#include <string.h>
+
+#include "internal.h"
+
+namespace ss {
+
+const int kPathDx[8] = {1, -1, 0, 0, 1, -1, 1, -1};
+const int kPathDy[8] = {0, 0, 1, -1, 1, 1, -1, -1};
+
+int pick_dpl(int max_disp)
+{
+    static const int options[] = {1, 2, 4, 6, 8, 12, 16};
+    for (int o : options)
+        if (kLanesPerLine * o >= max_disp) return o;
+    return 16;
+}
+
+int census_bits(int cw, int ch, int mode)
+{
+    const int n = cw * ch;
+    return mode == 0 ? (n - 1) / 2 : n - 1;
+}
+
+int path_lines(int dx, int dy, int W, int H) { return dy == 0 ? H : (dx == 0 ? W : W + H - 1); }
+
+static int validate(const simsense_params *p)
+{
+    if (!p) return SIMSENSE_ERR_NULL_POINTER;
+    if (p->struct_size != sizeof(simsense_params)) return SIMSENSE_ERR_ABI;
+    if (p->width < 1 || p->height < 1 || p->width > 8192 || p->height > 8192)
+        return SIMSENSE_ERR_INVALID_ARGUMENT;
+    if (p->max_disp < 1 || p->max_disp > 256) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    if (p->census_w < 1 || p->census_h < 1 || !(p->census_w & 1) || !(p->census_h & 1))
+        return SIMSENSE_ERR_INVALID_ARGUMENT;
+    if (p->census_mode != 0 && p->census_mode != 1) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    if (p->census_w * p->census_h < 3) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    const int bits = census_bits(p->census_w, p->census_h, p->census_mode);
+    if (bits > 64 || p->census_w > 65 || p->census_h > 65) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    if (p->p1 < 0 || p->p2 < p->p1 || bits + p->p2 > 255) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    if (p->uniqueness_pct < 0 || p->uniqueness_pct > 99) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    if (p->num_paths != 2 && p->num_paths != 4 && p->num_paths != 8) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    if (p->median != 0 && p->median != 3) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    if (p->subpixel != 0 && p->subpixel != 1) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    if (!(p->focal_px == p->focal_px) || !(p->baseline_m == p->baseline_m)) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    return SIMSENSE_OK;
+}
+
+struct Layout {
+    size_t census, paths, per_px[7], total;
+};
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static Layout layout(const simsense_params *p)
+{
+    Layout l{};
+    const size_t npx = (size_t)p->width * p->height;
+    const bool wide = census_bits(p->census_w, p->census_h, p->census_mode) > 32;
+    l.census = align256(npx * (wide ? 8 : 4));
+    l.paths = align256(npx * padded_disp(p->max_disp));
+    static const int px_bytes[7] = {1, 2, 2, 1, 4, 4, 1};  // dint, S1, S2, dright, dsub, masked, flags
+    l.total = 2 * l.census + (size_t)p->num_paths * l.paths;
+    for (int i = 0; i < 7; ++i) {
+        l.per_px[i] = align256(npx * px_bytes[i]);
+        l.total += l.per_px[i];
+    }
+    return l;
+}
+
+}  // namespace ss
+
+using namespace ss;
+
+struct simsense_handle {
+    simsense_params p;
+    int bits, Dpad, ndirs;
+    bool wide;
+    void *block;
+    void *census_l, *census_r;
+    uint8_t *paths[8];
+    uint8_t *disp_int, *disp_right, *flags_pre;
+    uint16_t *cost_best, *cost_second;
+    float *disp_sub, *masked;
+    hipStream_t last_stream;
+    // profiling: kProfSlots call slots of 2 events per pass
+    bool profiling;
+    int prof_used;
+    int prof_calls;
+    double prof_ms[SIMSENSE_NUM_PASSES];
+    hipEvent_t *prof_events;
+};
+
+namespace {
+constexpr int kProfSlots = 256;
+
+hipEvent_t *prof_slot(simsense_handle *h, int pass, bool end)
+{
+    return &h->prof_events[(size_t)h->prof_used * (2 * SIMSENSE_NUM_PASSES) + 2 * pass + (end ? 1 : 0)];
+}
+
+// waits for the recorded events and folds them into the accumulators
+int prof_harvest(simsense_handle *h)
+{
+    for (int c = 0; c < h->prof_used; ++c)
+        for (int p = 0; p < SIMSENSE_NUM_PASSES; ++p) {
+            hipEvent_t b = h->prof_events[(size_t)c * 2 * SIMSENSE_NUM_PASSES + 2 * p];
+            hipEvent_t e = h->prof_events[(size_t)c * 2 * SIMSENSE_NUM_PASSES + 2 * p + 1];
+            if (hipEventSynchronize(e) != hipSuccess) return SIMSENSE_ERR_DEVICE;
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, b, e) != hipSuccess) return SIMSENSE_ERR_DEVICE;
+            h->prof_ms[p] += ms;
+        }
+    h->prof_calls += h->prof_used;
+    h->prof_used = 0;
+    return SIMSENSE_OK;
+}
+
+void prof_free(simsense_handle *h)
+{
+    if (!h->prof_events) return;
+    for (int i = 0; i < kProfSlots * 2 * SIMSENSE_NUM_PASSES; ++i) (void)hipEventDestroy(h->prof_events[i]);
+    delete[] h->prof_events;
+    h->prof_events = nullptr;
+}
+}  // namespace
+
+extern "C" {
+
+const char *simsense_strerror(int status)
+{
+    switch (status) {
+    case SIMSENSE_OK: return "ok";
+    case SIMSENSE_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case SIMSENSE_ERR_NULL_POINTER: return "required pointer is NULL";
+    case SIMSENSE_ERR_OUT_OF_MEMORY: return "device out of memory";
+    case SIMSENSE_ERR_DEVICE: return "HIP runtime or kernel launch error";
+    case SIMSENSE_ERR_UNSUPPORTED: return "unsupported configuration";
+    case SIMSENSE_ERR_ABI: return "struct_size mismatch (ABI)";
+    default: return "unknown status";
+    }
+}
+
+int64_t simsense_scratch_bytes(const simsense_params *params)
+{
+    int rc = validate(params);
+    if (rc != SIMSENSE_OK) return rc;
+    return (int64_t)layout(params).total;
+}
+
+int simsense_create(const simsense_params *params, simsense_handle **out)
+{
+    if (!out) return SIMSENSE_ERR_NULL_POINTER;
+    int rc = validate(params);
+    if (rc != SIMSENSE_OK) return rc;
+    Layout l = layout(params);
+    simsense_handle *h = new (std::nothrow) simsense_handle();
+    if (!h) return SIMSENSE_ERR_OUT_OF_MEMORY;
+    h->p = *params;
+    h->bits = census_bits(params->census_w, params->census_h, params->census_mode);
+    h->wide = h->bits > 32;
+    h->Dpad = padded_disp(params->max_disp);
+    h->ndirs = params->num_paths;
+    if (hipMalloc(&h->block, l.total) != hipSuccess) {
+        (void)hipGetLastError();
+        delete h;
+        return SIMSENSE_ERR_OUT_OF_MEMORY;
+    }
+    uint8_t *cur = (uint8_t *)h->block;
+    h->census_l = cur; cur += l.census;
+    h->census_r = cur; cur += l.census;
+    for (int r = 0; r < h->ndirs; ++r) { h->paths[r] = cur; cur += l.paths; }
+    h->disp_int = cur; cur += l.per_px[0];
+    h->cost_best = (uint16_t *)cur; cur += l.per_px[1];
+    h->cost_second = (uint16_t *)cur; cur += l.per_px[2];
+    h->disp_right = cur; cur += l.per_px[3];
+    h->disp_sub = (float *)cur; cur += l.per_px[4];
+    h->masked = (float *)cur; cur += l.per_px[5];
+    h->flags_pre = cur; cur += l.per_px[6];
+    h->last_stream = nullptr;
+    h->profiling = false;
+    h->prof_events = nullptr;
+    h->prof_used = h->prof_calls = 0;
+    *out = h;
+    return SIMSENSE_OK;
+}
+
+int simsense_destroy(simsense_handle *h)
+{
+    if (!h) return SIMSENSE_OK;
+    int rc = SIMSENSE_OK;
+    if (hipStreamSynchronize(h->last_stream) != hipSuccess) rc = SIMSENSE_ERR_DEVICE;
+    if (hipFree(h->block) != hipSuccess) rc = SIMSENSE_ERR_DEVICE;
+    prof_free(h);
+    delete h;
+    return rc;
+}
+
+int simsense_compute_ex(simsense_handle *h, const uint8_t *left, const uint8_t *right, int32_t pitch,
+                        const simsense_outputs *o, void *stream)
+{
+    if (!h || !left || !right || !o) return SIMSENSE_ERR_NULL_POINTER;
+    const simsense_params &p = h->p;
+    if (pitch < p.width) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    hipStream_t s = (hipStream_t)stream;
+    h->last_stream = s;
+    const int W = p.width, H = p.height, D = p.max_disp;
+    const size_t npx = (size_t)W * H;
+#define SS_TRY(expr) \
+    do { if ((expr) != hipSuccess) { (void)hipGetLastError(); return SIMSENSE_ERR_DEVICE; } } while (0)
+    const bool prof = h->profiling;
+    if (prof && h->prof_used == kProfSlots) {
+        int rc = prof_harvest(h);
+        if (rc != SIMSENSE_OK) return rc;
+    }
+#define SS_MARK(pass, end) \
+    do { if (prof) SS_TRY(hipEventRecord(*prof_slot(h, pass, end), s)); } while (0)
+
+    SS_MARK(SIMSENSE_PASS_CENSUS, false);
+    SS_TRY(launch_census(left, pitch, W, H, p.census_w, p.census_h, p.census_mode, h->census_l, h->wide, s));
+    SS_TRY(launch_census(right, pitch, W, H, p.census_w, p.census_h, p.census_mode, h->census_r, h->wide, s));
+    SS_MARK(SIMSENSE_PASS_CENSUS, true);
+
+    AggregateArgs ag{};
+    ag.census_l = h->census_l;
+    ag.census_r = h->census_r;
+    ag.W = W; ag.H = H; ag.D = D; ag.Dpad = h->Dpad; ag.bits = h->bits; ag.p1 = p.p1; ag.p2 = p.p2;
+    ag.ndirs = h->ndirs;
+    ag.block_begin[0] = 0;
+    for (int r = 0; r < h->ndirs; ++r) {
+        ag.dx[r] = kPathDx[r];
+        ag.dy[r] = kPathDy[r];
+        ag.out[r] = h->paths[r];
+        const int lines = path_lines(kPathDx[r], kPathDy[r], W, H);
+        ag.block_begin[r + 1] = ag.block_begin[r] + (lines + kLinesPerBlock - 1) / kLinesPerBlock;
+    }
+    SS_MARK(SIMSENSE_PASS_AGGREGATE, false);
+    SS_TRY(launch_aggregate(ag, h->wide, s));
+    SS_MARK(SIMSENSE_PASS_AGGREGATE, true);
+
+    SelectArgs sa{};
+    for (int r = 0; r < h->ndirs; ++r) sa.paths[r] = h->paths[r];
+    sa.ndirs = h->ndirs;
+    sa.W = W; sa.H = H; sa.D = D; sa.Dpad = h->Dpad;
+    sa.uniqueness_pct = p.uniqueness_pct; sa.lr_max_diff = p.lr_max_diff; sa.subpixel = p.subpixel;
+    sa.disp_int = h->disp_int; sa.cost_best = h->cost_best; sa.cost_second = h->cost_second;
+    sa.disp_right = h->disp_right; sa.disp_sub = h->disp_sub; sa.masked = h->masked; sa.flags = h->flags_pre;
+    SS_MARK(SIMSENSE_PASS_SELECT, false);
+    SS_TRY(launch_select(sa, s));
+    SS_MARK(SIMSENSE_PASS_SELECT, true);
+
+    PostArgs pa{};
+    pa.masked = h->masked; pa.flags_in = h->flags_pre;
+    pa.W = W; pa.H = H; pa.median = p.median;
+    pa.fb = p.focal_px * p.baseline_m;
+    pa.disp = o->disp; pa.depth = o->depth; pa.flags = o->flags;
+    SS_MARK(SIMSENSE_PASS_POST, false);
+    if (pa.disp || pa.depth || pa.flags) SS_TRY(launch_post(pa, s));
+    SS_MARK(SIMSENSE_PASS_POST, true);
+    if (prof) ++h->prof_used;
+
+    if (o->disp_int) SS_TRY(hipMemcpyAsync(o->disp_int, h->disp_int, npx, hipMemcpyDeviceToDevice, s));
+    if (o->cost_best) SS_TRY(hipMemcpyAsync(o->cost_best, h->cost_best, npx * 2, hipMemcpyDeviceToDevice, s));
+    if (o->cost_second)
+        SS_TRY(hipMemcpyAsync(o->cost_second, h->cost_second, npx * 2, hipMemcpyDeviceToDevice, s));
+    if (o->disp_right) SS_TRY(hipMemcpyAsync(o->disp_right, h->disp_right, npx, hipMemcpyDeviceToDevice, s));
+    if (o->disp_sub) SS_TRY(hipMemcpyAsync(o->disp_sub, h->disp_sub, npx * 4, hipMemcpyDeviceToDevice, s));
+    if (o->census_left)
+        SS_TRY(launch_census(left, pitch, W, H, p.census_w, p.census_h, p.census_mode, o->census_left, true, s));
+    if (o->census_right)
+        SS_TRY(launch_census(right, pitch, W, H, p.census_w, p.census_h, p.census_mode, o->census_right, true, s));
+    if (o->volume) {
+        PathSet ps{};
+        for (int r = 0; r < h->ndirs; ++r) ps.p[r] = h->paths[r];
+        SS_TRY(launch_volume_sum(ps, h->ndirs, W, H, D, h->Dpad, o->volume, s));
+    }
+#undef SS_MARK
+#undef SS_TRY
+    return SIMSENSE_OK;
+}
+
+int simsense_profile_enable(simsense_handle *h, int enable)
+{
+    if (!h) return SIMSENSE_ERR_NULL_POINTER;
+    if (enable && !h->prof_events) {
+        const int n = kProfSlots * 2 * SIMSENSE_NUM_PASSES;
+        h->prof_events = new (std::nothrow) hipEvent_t[n]();
+        if (!h->prof_events) return SIMSENSE_ERR_OUT_OF_MEMORY;
+        for (int i = 0; i < n; ++i)
+            if (hipEventCreate(&h->prof_events[i]) != hipSuccess) {
+                (void)hipGetLastError();
+                for (int k = 0; k < i; ++k) (void)hipEventDestroy(h->prof_events[k]);
+                delete[] h->prof_events;
+                h->prof_events = nullptr;
+                return SIMSENSE_ERR_DEVICE;
+            }
+        h->prof_used = h->prof_calls = 0;
+        for (double &v : h->prof_ms) v = 0.0;
+    }
+    h->profiling = enable != 0;
+    return SIMSENSE_OK;
+}
+
+int simsense_profile_read(simsense_handle *h, double *ms, int32_t *calls, int32_t n)
+{
+    if (!h || !ms || !calls) return SIMSENSE_ERR_NULL_POINTER;
+    if (n < 0) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    if (h->prof_events) {
+        int rc = prof_harvest(h);
+        if (rc != SIMSENSE_OK) return rc;
+    }
+    for (int i = 0; i < n && i < SIMSENSE_NUM_PASSES; ++i) ms[i] = h->prof_ms[i];
+    *calls = h->prof_calls;
+    for (double &v : h->prof_ms) v = 0.0;
+    h->prof_calls = 0;
+    return SIMSENSE_OK;
+}
+
+int simsense_compute(simsense_handle *h, const uint8_t *left, const uint8_t *right, int32_t pitch, float *depth,
+                     float *disp, uint8_t *flags, void *stream)
+{
+    if (!depth) return SIMSENSE_ERR_NULL_POINTER;
+    simsense_outputs o{};
+    o.depth = depth;
+    o.disp = disp;
+    o.flags = flags;
+    return simsense_compute_ex(h, left, right, pitch, &o, stream);
+}
+
+int simsense_ir_noise(const uint8_t *in, const float *gamma, const float *n, uint8_t *out, int64_t count,
+                      void *stream)
+{
+    if (count < 0) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    if (count == 0) return SIMSENSE_OK;
+    if (!in || !gamma || !n || !out) return SIMSENSE_ERR_NULL_POINTER;
+    if (launch_ir_noise(in, gamma, n, out, count, (hipStream_t)stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return SIMSENSE_ERR_DEVICE;
+    }
+    return SIMSENSE_OK;
+}
+
+int simsense_census(const simsense_params *params, const uint8_t *img, int32_t pitch, uint64_t *out,
+                    void *stream)
+{
+    int rc = validate(params);
+    if (rc != SIMSENSE_OK) return rc;
+    if (!img || !out) return SIMSENSE_ERR_NULL_POINTER;
+    if (pitch < params->width) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    if (launch_census(img, pitch, params->width, params->height, params->census_w, params->census_h,
+                      params->census_mode, out, true, (hipStream_t)stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return SIMSENSE_ERR_DEVICE;
+    }
+    return SIMSENSE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,100 @@
+// IR noise model (Sec. VI-C, Eq. (7)) and census transform (Sec. VI-D).
+#include "internal.h"
+
+namespace ss {
+
+// ---------------------------------------------------------------- IR noise
+// out = clip(rint(gamma * in + n), 0, 255); product and sum are separately
+// rounded fp32 operations, the integer decision is a round-half-even.
+__global__ __launch_bounds__(256) void ir_noise_kernel(const uint8_t *__restrict__ in,
+                                                       const float *__restrict__ gamma,
+                                                       const float *__restrict__ n,
+                                                       uint8_t *__restrict__ out, int64_t count)
+{
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+        float v = __fadd_rn(__fmul_rn(gamma[i], (float)in[i]), n[i]);
+        float r = rintf(v);
+        r = r > 0.0f ? r : 0.0f;  // also maps NaN to 0
+        r = r < 255.0f ? r : 255.0f;
+        out[i] = (uint8_t)r;
+    }
+}
+
+hipError_t launch_ir_noise(const uint8_t *in, const float *gamma, const float *n, uint8_t *out,
+                           int64_t count, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(ir_noise_kernel, dim3((unsigned)blocks), dim3(256), 0, s, in, gamma, n, out, count);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- census
+// A 32x8 output tile per block; the tile plus its window halo is staged in LDS
+// with clamp-to-edge addressing, then each thread walks its window.  Bit k of a
+// word is the k-th comparison of the window in row-major order:
+//   full:               [I(p) > I(p+o)]       for every o != 0
+//   center-symmetric:   [I(p+o) > I(p-o)]     for every o before the centre
+constexpr int kCensusTx = 32, kCensusTy = 8;
+
+template <typename Word>
+__global__ __launch_bounds__(256) void census_kernel(const uint8_t *__restrict__ img, int pitch, int W,
+                                                     int H, int cw, int ch, int mode,
+                                                     Word *__restrict__ out)
+{
+    extern __shared__ uint8_t tile[];
+    const int rw = cw / 2, rh = ch / 2;
+    const int tw = kCensusTx + cw - 1, th = kCensusTy + ch - 1;
+    const int x0 = blockIdx.x * kCensusTx - rw, y0 = blockIdx.y * kCensusTy - rh;
+    const int tid = threadIdx.y * kCensusTx + threadIdx.x;
+    for (int i = tid; i < tw * th; i += kCensusTx * kCensusTy) {
+        int ty = i / tw, tx = i - ty * tw;
+        int gx = min(max(x0 + tx, 0), W - 1), gy = min(max(y0 + ty, 0), H - 1);
+        tile[i] = img[(size_t)gy * pitch + gx];
+    }
+    __syncthreads();
+    const int x = blockIdx.x * kCensusTx + threadIdx.x, y = blockIdx.y * kCensusTy + threadIdx.y;
+    if (x >= W || y >= H) return;
+    // window centre inside the tile
+    const int cx = threadIdx.x + rw, cy = threadIdx.y + rh;
+    Word word = 0;
+    int k = 0;
+    if (mode == 0) {
+        const int half = (cw * ch - 1) / 2;
+        for (int i = 0; i < half; ++i) {
+            int oy = i / cw - rh, ox = i % cw - rw;
+            int a = tile[(cy + oy) * tw + cx + ox];
+            int b = tile[(cy - oy) * tw + cx - ox];
+            word |= (Word)(a > b) << k;
+            ++k;
+        }
+    } else {
+        const int c = tile[cy * tw + cx];
+        for (int oy = -rh; oy <= rh; ++oy)
+            for (int ox = -rw; ox <= rw; ++ox) {
+                if (ox == 0 && oy == 0) continue;
+                word |= (Word)(c > tile[(cy + oy) * tw + cx + ox]) << k;
+                ++k;
+            }
+    }
+    out[(size_t)y * W + x] = word;
+}
+
+hipError_t launch_census(const uint8_t *img, int pitch, int W, int H, int cw, int ch, int mode, void *out,
+                         bool out64, hipStream_t s)
+{
+    dim3 grid((W + kCensusTx - 1) / kCensusTx, (H + kCensusTy - 1) / kCensusTy);
+    dim3 block(kCensusTx, kCensusTy);
+    size_t lds = (size_t)(kCensusTx + cw - 1) * (kCensusTy + ch - 1);
+    if (out64)
+        hipLaunchKernelGGL(census_kernel<uint64_t>, grid, block, lds, s, img, pitch, W, H, cw, ch, mode,
+                           (uint64_t *)out);
+    else
+        hipLaunchKernelGGL(census_kernel<uint32_t>, grid, block, lds, s, img, pitch, W, H, cw, ch, mode,
+                           (uint32_t *)out);
+    return hipGetLastError();
+}
+
+}  // namespace ss

@@ -1,0 +1,74 @@
+// Internal declarations shared by the library's translation units (not installed).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/simsense.h"
+
+namespace ss {
+
+// Lanes that cooperate on one scanline: exactly one DPP row of a wave64, so
+// every cross-lane step of the path recurrence is a row-local DPP operation.
+constexpr int kLanesPerLine = 16;
+constexpr int kLinesPerBlock = 16;  // 256-thread blocks
+constexpr int kBlock = kLanesPerLine * kLinesPerBlock;
+
+// Disparities held by each lane; the padded disparity count is 16 * dpl.
+int pick_dpl(int max_disp);
+inline int padded_disp(int max_disp) { return kLanesPerLine * pick_dpl(max_disp); }
+int census_bits(int cw, int ch, int mode);
+
+// Path directions: 2 paths = horizontal pair, 4 adds the vertical pair, 8 adds
+// the four diagonals (same order as the header documents).
+extern const int kPathDx[8];
+extern const int kPathDy[8];
+int path_lines(int dx, int dy, int W, int H);
+
+struct AggregateArgs {
+    const void *census_l, *census_r;  // uint32 words, or uint64 when bits > 32
+    int W, H, D, Dpad, bits, p1, p2;
+    int ndirs;
+    int dx[8], dy[8];
+    int block_begin[9];  // first block index of each direction, prefix sums
+    uint8_t *out[8];     // per-direction path values, W*H*Dpad bytes, d fastest
+};
+
+struct SelectArgs {
+    const uint8_t *paths[8];
+    int ndirs;
+    int W, H, D, Dpad;
+    int uniqueness_pct, lr_max_diff, subpixel;
+    uint8_t *disp_int;    // W*H
+    uint16_t *cost_best;  // W*H
+    uint16_t *cost_second;
+    uint8_t *disp_right;
+    float *disp_sub;      // before masking
+    float *masked;        // masked sub-pixel disparity (0 = invalid)
+    uint8_t *flags;       // bits 0..2
+};
+
+struct PostArgs {
+    const float *masked;
+    const uint8_t *flags_in;
+    int W, H, median;
+    float fb;
+    float *disp;     // may be null
+    float *depth;    // may be null
+    uint8_t *flags;  // may be null
+};
+
+hipError_t launch_ir_noise(const uint8_t *in, const float *gamma, const float *n, uint8_t *out,
+                           int64_t count, hipStream_t s);
+hipError_t launch_census(const uint8_t *img, int pitch, int W, int H, int cw, int ch, int mode,
+                         void *out, bool out64, hipStream_t s);
+hipError_t launch_aggregate(const AggregateArgs &a, bool wide, hipStream_t s);
+hipError_t launch_select(const SelectArgs &a, hipStream_t s);
+hipError_t launch_post(const PostArgs &a, hipStream_t s);
+struct PathSet {
+    const uint8_t *p[8];
+};
+hipError_t launch_volume_sum(const PathSet &paths, int ndirs, int W, int H, int D, int Dpad,
+                             uint16_t *out, hipStream_t s);
+
+}  // namespace ss

@@ -1,0 +1,207 @@
+"""ctypes binding of ``libsimsense.so`` (argument marshalling only).
+
+Every step of the depth path runs in the HIP library; this module only turns
+torch tensors into device pointers and the current torch stream into a
+hipStream_t.  If the library has not been built the import fails loudly:
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from typing import Dict, Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsimsense.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it first (python -m paper_2201_11924_amd.build)")
+
+_lib = ct.CDLL(LIB_PATH)
+
+OK = 0
+STATUS = {0: "ok", -1: "invalid argument", -2: "null pointer", -3: "out of memory", -4: "device error",
+          -5: "unsupported", -6: "abi mismatch"}
+FLAG_UNIQUE, FLAG_LR, FLAG_NONZERO, FLAG_VALID = 1, 2, 4, 8
+
+PARAM_FIELDS = ("width", "height", "max_disp", "census_w", "census_h", "census_mode", "p1", "p2",
+                "uniqueness_pct", "lr_max_diff", "num_paths", "median", "subpixel")
+
+
+class Params(ct.Structure):
+    _fields_ = [("struct_size", ct.c_uint32)] + [(n, ct.c_int32) for n in PARAM_FIELDS] + [
+        ("focal_px", ct.c_float), ("baseline_m", ct.c_float)]
+
+    @classmethod
+    def from_dict(cls, d: Dict) -> "Params":
+        p = cls()
+        p.struct_size = ct.sizeof(cls)
+        for n in PARAM_FIELDS:
+            setattr(p, n, int(d[n]))
+        p.focal_px = float(d["focal_px"])
+        p.baseline_m = float(d["baseline_m"])
+        return p
+
+
+class Outputs(ct.Structure):
+    _fields_ = [(n, ct.c_void_p) for n in (
+        "depth", "disp", "flags", "disp_int", "cost_best", "cost_second", "disp_right", "disp_sub",
+        "census_left", "census_right", "volume")]
+
+
+_vp, _i32, _i64 = ct.c_void_p, ct.c_int32, ct.c_int64
+_lib.simsense_create.argtypes = [ct.POINTER(Params), ct.POINTER(_vp)]
+_lib.simsense_destroy.argtypes = [_vp]
+_lib.simsense_compute.argtypes = [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp]
+_lib.simsense_compute_ex.argtypes = [_vp, _vp, _vp, _i32, ct.POINTER(Outputs), _vp]
+_lib.simsense_ir_noise.argtypes = [_vp, _vp, _vp, _vp, _i64, _vp]
+_lib.simsense_census.argtypes = [ct.POINTER(Params), _vp, _i32, _vp, _vp]
+_lib.simsense_strerror.argtypes = [ct.c_int]
+_lib.simsense_strerror.restype = ct.c_char_p
+_lib.simsense_scratch_bytes.argtypes = [ct.POINTER(Params)]
+_lib.simsense_scratch_bytes.restype = _i64
+_lib.simsense_profile_enable.argtypes = [_vp, ct.c_int]
+_lib.simsense_profile_read.argtypes = [_vp, ct.POINTER(ct.c_double), ct.POINTER(_i32), _i32]
+PASSES = ("census", "aggregate", "select", "post")
+
+
+class SimSenseError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {_lib.simsense_strerror(code).decode()} ({code})")
+        self.code = code
+
+
+def _check(code: int, what: str) -> None:
+    if code != OK:
+        raise SimSenseError(code, what)
+
+
+def lib() -> ct.CDLL:
+    return _lib
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensors passed to the HIP library must live on the GPU")
+    return ct.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ct.c_void_p(s.cuda_stream)
+
+
+def _need(t: torch.Tensor, dtype, shape, name):
+    if t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous() or not t.is_cuda:
+        raise ValueError(f"{name}: need a contiguous {dtype} GPU tensor of shape {tuple(shape)}, got "
+                         f"{t.dtype} {tuple(t.shape)} on {t.device}")
+
+
+def scratch_bytes(params: Dict) -> int:
+    p = Params.from_dict(params)
+    v = _lib.simsense_scratch_bytes(ct.byref(p))
+    if v < 0:
+        _check(int(v), "simsense_scratch_bytes")
+    return int(v)
+
+
+class SimSense:
+    """One parameter set of the depth path and its device scratch."""
+
+    def __init__(self, params: Dict):
+        self.params = dict(params)
+        self._p = Params.from_dict(params)
+        h = ct.c_void_p()
+        _check(_lib.simsense_create(ct.byref(self._p), ct.byref(h)), "simsense_create")
+        self._h = h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _check(_lib.simsense_destroy(self._h), "simsense_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def profile(self, enable: bool = True) -> None:
+        _check(_lib.simsense_profile_enable(self._h, int(enable)), "simsense_profile_enable")
+
+    def profile_read(self):
+        """(calls, {pass: total device ms}) since the last read."""
+        ms = (ct.c_double * len(PASSES))()
+        calls = _i32()
+        _check(_lib.simsense_profile_read(self._h, ms, ct.byref(calls), len(PASSES)), "simsense_profile_read")
+        return calls.value, dict(zip(PASSES, list(ms)))
+
+    @property
+    def shape(self):
+        return (self.params["height"], self.params["width"])
+
+    def compute(self, left: torch.Tensor, right: torch.Tensor, depth: torch.Tensor,
+                disp: Optional[torch.Tensor] = None, flags: Optional[torch.Tensor] = None, stream=None):
+        H, W = self.shape
+        _need(left, torch.uint8, (H, W), "left")
+        _need(right, torch.uint8, (H, W), "right")
+        _need(depth, torch.float32, (H, W), "depth")
+        _check(_lib.simsense_compute(self._h, _ptr(left), _ptr(right), W, _ptr(depth), _ptr(disp),
+                                     _ptr(flags), _stream(stream)), "simsense_compute")
+
+    def __call__(self, left: torch.Tensor, right: torch.Tensor, stream=None):
+        H, W = self.shape
+        depth = torch.empty((H, W), dtype=torch.float32, device=left.device)
+        disp = torch.empty_like(depth)
+        flags = torch.empty((H, W), dtype=torch.uint8, device=left.device)
+        self.compute(left, right, depth, disp, flags, stream)
+        return depth, disp, flags
+
+    def compute_all(self, left: torch.Tensor, right: torch.Tensor, volume: bool = False, stream=None):
+        """Every intermediate of the path, as a dict of GPU tensors."""
+        H, W = self.shape
+        D = self.params["max_disp"]
+        dev = left.device
+        _need(left, torch.uint8, (H, W), "left")
+        _need(right, torch.uint8, (H, W), "right")
+        out = dict(depth=torch.empty((H, W), dtype=torch.float32, device=dev),
+                   disp=torch.empty((H, W), dtype=torch.float32, device=dev),
+                   flags=torch.empty((H, W), dtype=torch.uint8, device=dev),
+                   disp_int=torch.empty((H, W), dtype=torch.uint8, device=dev),
+                   cost_best=torch.empty((H, W), dtype=torch.int16, device=dev),
+                   cost_second=torch.empty((H, W), dtype=torch.int16, device=dev),
+                   disp_right=torch.empty((H, W), dtype=torch.uint8, device=dev),
+                   disp_sub=torch.empty((H, W), dtype=torch.float32, device=dev),
+                   census_left=torch.empty((H, W), dtype=torch.int64, device=dev),
+                   census_right=torch.empty((H, W), dtype=torch.int64, device=dev))
+        if volume:
+            out["volume"] = torch.empty((H, W, D), dtype=torch.int16, device=dev)
+        o = Outputs(**{k: v.data_ptr() for k, v in out.items()})
+        _check(_lib.simsense_compute_ex(self._h, _ptr(left), _ptr(right), W, ct.byref(o), _stream(stream)),
+               "simsense_compute_ex")
+        return out
+
+
+def ir_noise(img: torch.Tensor, gamma: torch.Tensor, n: torch.Tensor, out: Optional[torch.Tensor] = None,
+             stream=None) -> torch.Tensor:
+    """IR noise model of Sec. VI-C, Eq. (7), applied with the caller's draws."""
+    _need(gamma, torch.float32, img.shape, "gamma")
+    _need(n, torch.float32, img.shape, "n")
+    _need(img, torch.uint8, img.shape, "img")
+    out = torch.empty_like(img) if out is None else out
+    _check(_lib.simsense_ir_noise(_ptr(img), _ptr(gamma), _ptr(n), _ptr(out), img.numel(), _stream(stream)),
+           "simsense_ir_noise")
+    return out
+
+
+def census(params: Dict, img: torch.Tensor, stream=None) -> torch.Tensor:
+    p = Params.from_dict(params)
+    H, W = params["height"], params["width"]
+    _need(img, torch.uint8, (H, W), "img")
+    out = torch.empty((H, W), dtype=torch.int64, device=img.device)
+    _check(_lib.simsense_census(ct.byref(p), _ptr(img), W, _ptr(out), _stream(stream)), "simsense_census")
+    return out
