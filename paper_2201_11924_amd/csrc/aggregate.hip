@@ -6,8 +6,8 @@
 // Every scanline of every direction is an independent sequence, so each one is
 // given to 16 lanes (one DPP row of a wave64) that hold its D-vector, dpl
 // consecutive disparities per lane.  A step of the recurrence is then:
-//   * the matching cost recomputed from the census words (XOR + popcount), so
-//     no cost volume is ever written;
+//   * the matching cost recomputed from census words held in LDS (XOR +
+//     popcount), so no cost volume is ever written;
 //   * the d-1 / d+1 neighbours from the lane's own registers, and at the lane
 //     edges through a row_shr / row_shl DPP move;
 //   * the path minimum m through a row_ror butterfly (4 DPP steps);
@@ -16,8 +16,19 @@
 // equals the recurrence above exactly; a line starts from Q = 0, which yields
 // L = C at its first pixel.
 //
+// A 256-thread block owns 16 lines of one direction and advances them by one
+// "clock" at a time.  Lines are grouped so that at every clock the block's 16
+// pixels lie in one image row and 16 consecutive columns (vertical lines, and
+// diagonals entering through the top/bottom row), or all in one column of 16
+// consecutive rows (horizontal lines).  Diagonals entering through a side column
+// are started one clock apart so they also share a row.  The census words a
+// block needs for 16 clocks are then a 16 x (Dpad + 31) word tile: it is loaded
+// from global memory while the previous 16 clocks are computed from the other
+// half of a double-buffered LDS tile, so the scanline loop waits on global
+// memory only once per 16 steps.
+//
 // Each direction writes its path values (<= bits + P2 <= 255) as bytes into a
-// buffer of its own; the selection pass sums the directions.
+// buffer of its own, d fastest; the selection pass sums the directions.
 #include "internal.h"
 
 namespace ss {
@@ -26,6 +37,8 @@ namespace {
 
 constexpr uint32_t kInf = 0x10000000u;      // outside the disparity range
 constexpr uint32_t kPadCost = 0x01000000u;  // cost of the padding disparities >= D
+constexpr int kChunk = 16;                  // clocks per LDS tile (= lines per block)
+static_assert(kChunk == kLinesPerBlock, "one tile slot per line");
 
 // DPP controls (GFX9 encoding)
 constexpr int kRowShl1 = 0x101, kRowShr1 = 0x111;
@@ -37,13 +50,20 @@ __device__ __forceinline__ uint32_t dpp_mov(uint32_t old, uint32_t v)
     return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, 0xF, 0xF, false);
 }
 
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_rot(uint32_t v)
+{
+    // a row rotation reads a valid lane for every lane, so no old value is needed
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, true);
+}
+
 // minimum over the 16 lanes of a DPP row, returned in every lane of the row
 __device__ __forceinline__ uint32_t row_min(uint32_t v)
 {
-    v = min(v, dpp_mov<kRowRor8>(v, v));
-    v = min(v, dpp_mov<kRowRor4>(v, v));
-    v = min(v, dpp_mov<kRowRor2>(v, v));
-    v = min(v, dpp_mov<kRowRor1>(v, v));
+    v = min(v, dpp_rot<kRowRor8>(v));
+    v = min(v, dpp_rot<kRowRor4>(v));
+    v = min(v, dpp_rot<kRowRor2>(v));
+    v = min(v, dpp_rot<kRowRor1>(v));
     return v;
 }
 
@@ -60,46 +80,18 @@ struct CensusWord<true> {
     static __device__ __forceinline__ uint32_t hamming(T a, T b) { return __popcll(a ^ b); }
 };
 
-struct Line {
-    int x, y, len;
-};
-
-__device__ __forceinline__ Line line_geometry(int dx, int dy, int i, int W, int H)
-{
-    Line ln;
-    if (dy == 0) {
-        ln.y = i;
-        ln.x = dx > 0 ? 0 : W - 1;
-        ln.len = W;
-    } else if (dx == 0) {
-        ln.x = i;
-        ln.y = dy > 0 ? 0 : H - 1;
-        ln.len = H;
-    } else {
-        const int ye = dy > 0 ? 0 : H - 1, xe = dx > 0 ? 0 : W - 1;
-        if (i < W) {
-            ln.x = i;
-            ln.y = ye;
-        } else {
-            ln.x = xe;
-            ln.y = ye + dy * (i - W + 1);
-        }
-        const int lx = dx > 0 ? W - ln.x : ln.x + 1;
-        const int ly = dy > 0 ? H - ln.y : ln.y + 1;
-        ln.len = min(lx, ly);
-    }
-    return ln;
-}
-
 template <int DPL>
 __device__ __forceinline__ void store_bytes(uint8_t *dst, const uint32_t (&L)[DPL])
 {
     if constexpr (DPL % 4 == 0) {
         uint32_t w[DPL / 4];
 #pragma unroll
-        for (int k = 0; k < DPL / 4; ++k)
-            w[k] = (L[4 * k] & 0xFF) | ((L[4 * k + 1] & 0xFF) << 8) | ((L[4 * k + 2] & 0xFF) << 16) |
-                   (L[4 * k + 3] << 24);
+        for (int k = 0; k < DPL / 4; ++k) {
+            // low bytes of L0..L3 into one word: two byte-pair gathers, then one merge
+            const uint32_t lo = __builtin_amdgcn_perm(L[4 * k + 1], L[4 * k], 0x0c0c0400u);
+            const uint32_t hi = __builtin_amdgcn_perm(L[4 * k + 3], L[4 * k + 2], 0x0c0c0400u);
+            w[k] = __builtin_amdgcn_perm(hi, lo, 0x05040100u);
+        }
         if constexpr (DPL == 4) {
             *(uint32_t *)dst = w[0];
         } else if constexpr (DPL == 8) {
@@ -121,67 +113,246 @@ __device__ __forceinline__ void store_bytes(uint8_t *dst, const uint32_t (&L)[DP
     }
 }
 
+// Geometry of one block of 16 lines of one direction.
+//  kind 0: horizontal; the 16 lines are rows r0..r0+15 and every line is at
+//          column xs + t*dx at clock t;
+//  kind 1: vertical, or diagonal entering through the top/bottom row ye: line i
+//          starts at column g0 + i; at clock t every line is in row ye + t*dy and
+//          line i in column g0 + t*dx + i;
+//  kind 2: diagonal entering through the side column xe: line i starts at row
+//          ye + dy*(j0 + i + 1) and runs one clock behind line i-1, so at clock t
+//          every line is in row ye + dy*(j0 + 1 + t).
+struct BlockGeom {
+    int kind, dx, dy;
+    int r0, g0, j0;
+    int xs, xe, ye;
+    int clocks;  // clocks the block runs
+    int nvalid;  // lines of the block that exist
+};
+
+__device__ __forceinline__ BlockGeom block_geometry(int dx, int dy, int blk, int W, int H)
+{
+    BlockGeom g{};
+    g.dx = dx;
+    g.dy = dy;
+    g.ye = dy > 0 ? 0 : H - 1;
+    g.xe = dx > 0 ? 0 : W - 1;
+    if (dy == 0) {
+        g.kind = 0;
+        g.r0 = blk * kChunk;
+        g.xs = dx > 0 ? 0 : W - 1;
+        g.clocks = W;
+        g.nvalid = min(kChunk, H - g.r0);
+    } else {
+        const int top_blocks = (W + kChunk - 1) / kChunk;
+        if (dx == 0 || blk < top_blocks) {
+            g.kind = 1;
+            g.g0 = blk * kChunk;
+            g.nvalid = min(kChunk, W - g.g0);
+            if (dx == 0) {
+                g.clocks = H;
+            } else {
+                // the longest line of the block starts farthest from its exit column
+                const int lfirst = dx > 0 ? W - g.g0 : g.g0 + 1;
+                const int llast = dx > 0 ? W - (g.g0 + g.nvalid - 1) : g.g0 + g.nvalid;
+                g.clocks = min(max(lfirst, llast), H);
+            }
+        } else {
+            g.kind = 2;
+            g.j0 = (blk - top_blocks) * kChunk;
+            g.nvalid = min(kChunk, H - 1 - g.j0);
+            int c = 0;  // line i: skew i, length min(W, H - j0 - i - 1)
+            for (int i = 0; i < g.nvalid; ++i) c = max(c, i + min(W, H - g.j0 - i - 1));
+            g.clocks = c;
+        }
+    }
+    return g;
+}
+
+// row and leftmost column of the block's 16-column window at clock t (kinds 1, 2)
+__device__ __forceinline__ void window_at(const BlockGeom &g, int t, int &row, int &xm)
+{
+    if (g.kind == 1) {
+        row = g.ye + t * g.dy;
+        xm = g.g0 + t * g.dx;
+    } else {
+        row = g.ye + g.dy * (g.j0 + 1 + t);
+        xm = g.dx > 0 ? g.xe + t - (kChunk - 1) : g.xe - t;
+    }
+}
+
 }  // namespace
 
-template <int DPL, bool WIDE>
-__global__ __launch_bounds__(kBlock) void aggregate_kernel(AggregateArgs a)
+// One block's scanlines, specialised by line kind (see BlockGeom).  The output
+// buffer holds one spare pixel after the image: lanes of lines that have ended
+// (or not started yet) store there, so every step issues the same unconditional
+// store and the loop carries no branch.
+template <int DPL, bool WIDE, int KIND>
+__device__ __forceinline__ void run_lines(const AggregateArgs &a, const BlockGeom &g, uint8_t *__restrict__ out,
+                                          typename CensusWord<WIDE>::T (*tile)[kLinesPerBlock * (kLanesPerLine * DPL + 2 * kChunk - 1)])
 {
     using CW = CensusWord<WIDE>;
     using Word = typename CW::T;
-    // which direction this block serves (uniform)
-    int dir = 0;
-#pragma unroll
-    for (int k = 1; k < 8; ++k)
-        if (k < a.ndirs && (int)blockIdx.x >= a.block_begin[k]) dir = k;
-    const int dx = a.dx[dir], dy = a.dy[dir];
-    const int lane = threadIdx.x % kLanesPerLine;
-    const int line = ((int)blockIdx.x - a.block_begin[dir]) * kLinesPerBlock + threadIdx.x / kLanesPerLine;
-    const int W = a.W, H = a.H;
-    const int nlines = dy == 0 ? H : (dx == 0 ? W : W + H - 1);
-    if (line >= nlines) return;  // whole DPP rows leave together
-    Line ln = line_geometry(dx, dy, line, W, H);
-
+    constexpr int kDpad = kLanesPerLine * DPL;
+    constexpr int kSlot = kDpad + 2 * kChunk - 1;  // cR window (Dpad + 15) then cL window (16)
+    constexpr int kTile = kChunk * kSlot;
+    constexpr int kPerThread = (kTile + kBlock - 1) / kBlock;
+    const int W = a.W, H = a.H, D = a.D;
+    const int lane = threadIdx.x % kLanesPerLine, li = threadIdx.x / kLanesPerLine;
+    const int d0 = lane * DPL;
     const Word *__restrict__ cl = (const Word *)a.census_l;
     const Word *__restrict__ cr = (const Word *)a.census_r;
-    uint8_t *__restrict__ out = a.out[dir];
-    const int d0 = lane * DPL;
     const uint32_t p1 = a.p1, p2 = a.p2, bits = a.bits;
-    const int D = a.D, Dpad = a.Dpad;
+    const bool padded = D < kDpad;
+    const size_t trash = (size_t)W * H * kDpad + d0;
+
+    int len = 0, skew = 0;
+    if (li < g.nvalid) {
+        if (KIND == 0) {
+            len = W;
+        } else if (KIND == 1) {
+            const int x0 = g.g0 + li;
+            len = g.dx == 0 ? H : min(g.dx > 0 ? W - x0 : x0 + 1, H);
+        } else {
+            skew = li;
+            len = min(W, H - g.j0 - li - 1);
+        }
+    }
+
+    // row and leftmost column of the 16-column window of tile slot `slot`
+    auto slot_window = [&](int c0, int slot, int &row, int &xm) {
+        if (KIND == 0) {
+            row = g.r0 + slot;
+            const int xc = g.xs + c0 * g.dx;
+            xm = g.dx > 0 ? xc : xc - (kChunk - 1);
+        } else if (KIND == 1) {
+            row = g.ye + (c0 + slot) * g.dy;
+            xm = g.g0 + (c0 + slot) * g.dx;
+        } else {
+            const int t = c0 + slot;
+            row = g.ye + g.dy * (g.j0 + 1 + t);
+            xm = g.dx > 0 ? g.xe + t - (kChunk - 1) : g.xe - t;
+        }
+    };
+    auto stage_load = [&](int c0, Word(&v)[kPerThread]) {
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k) {
+            const int q = threadIdx.x + k * kBlock;
+            const int slot = q / kSlot, idx = q - slot * kSlot;
+            int row, xm;
+            slot_window(c0, slot, row, xm);
+            const bool is_left = idx >= kDpad + kChunk - 1;
+            int col = is_left ? xm + idx - (kDpad + kChunk - 1) : xm - kDpad + 1 + idx;
+            row = min(max(row, 0), H - 1);
+            col = min(max(col, 0), W - 1);
+            const Word *src = is_left ? cl : cr;
+            v[k] = q < kTile ? src[(size_t)row * W + col] : Word(0);
+        }
+    };
+    auto stage_store = [&](int buf, const Word(&v)[kPerThread]) {
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k) {
+            const int q = threadIdx.x + k * kBlock;
+            if (q < kTile) tile[buf][q] = v[k];
+        }
+    };
 
     uint32_t Q[DPL];
 #pragma unroll
     for (int j = 0; j < DPL; ++j) Q[j] = 0;
 
-    int x = ln.x, y = ln.y;
-    for (int s = 0; s < ln.len; ++s, x += dx, y += dy) {
-        const size_t row = (size_t)y * W;
-        const Word wl = cl[row + x];
-        uint32_t C[DPL];
+    Word staged[kPerThread];
+    stage_load(0, staged);
+    stage_store(0, staged);
+    __syncthreads();
+
+    const int nchunks = (g.clocks + kChunk - 1) / kChunk;
+    for (int c = 0; c < nchunks; ++c) {
+        const int buf = c & 1;
+        const int c0 = c * kChunk;
+        if (c + 1 < nchunks) stage_load(c0 + kChunk, staged);
 #pragma unroll
-        for (int j = 0; j < DPL; ++j) {
-            const int d = d0 + j;
-            const int xr = x - d;
-            // the load is unconditional (clamped index) so all dpl loads issue together
-            const uint32_t c = CW::hamming(wl, cr[row + max(xr, 0)]);
-            C[j] = d < D ? (xr >= 0 ? c : bits) : kPadCost;
+        for (int k = 0; k < kChunk; ++k) {
+            const int t = c0 + k;
+            const int s = t - skew;
+            int x, row, xm;
+            const int slot = KIND == 0 ? li : k;
+            slot_window(c0, slot, row, xm);
+            if (KIND == 0) x = g.xs + t * g.dx;
+            else if (KIND == 1) x = xm + li;
+            else x = xm + (g.dx > 0 ? kChunk - 1 - li : li);
+            const bool active = s >= 0 && s < len;
+            const Word *sl = &tile[buf][slot * kSlot];
+            const int xo = x - xm;  // 0..15 for every lane
+            const Word wl = sl[kDpad + kChunk - 1 + xo];
+            // words for d = d0 + DPL - 1 .. d0 sit at increasing addresses from here
+            const Word *wr = sl + (xo + kDpad - d0 - DPL);
+            const uint32_t qm_edge = dpp_mov<kRowShr1>(kInf, Q[DPL - 1]);
+            const uint32_t qp_edge = dpp_mov<kRowShl1>(kInf, Q[0]);
+            uint32_t L[DPL];
+            uint32_t m = 0xFFFFFFFFu;
+            // the block's leftmost column decides whether any lane sees x - d < 0
+            const bool border = padded || (KIND == 0 ? x : xm) < kDpad - 1;
+            if (!border) {
+#pragma unroll
+                for (int j = 0; j < DPL; ++j) {
+                    const uint32_t qm = j > 0 ? Q[j - 1] : qm_edge;
+                    const uint32_t qp = j < DPL - 1 ? Q[j + 1] : qp_edge;
+                    const uint32_t tt = min(min(Q[j], min(qm, qp) + p1), p2);
+                    L[j] = tt + CW::hamming(wl, wr[DPL - 1 - j]);
+                    m = min(m, L[j]);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < DPL; ++j) {
+                    const int d = d0 + j;
+                    const uint32_t cst = CW::hamming(wl, wr[DPL - 1 - j]);
+                    const uint32_t C = d < D ? (x - d >= 0 ? cst : bits) : kPadCost;
+                    const uint32_t qm = j > 0 ? Q[j - 1] : qm_edge;
+                    const uint32_t qp = j < DPL - 1 ? Q[j + 1] : qp_edge;
+                    const uint32_t tt = min(min(Q[j], min(qm, qp) + p1), p2);
+                    L[j] = tt + C;
+                    m = min(m, L[j]);
+                }
+            }
+            m = row_min(m);
+            if (KIND == 2 && c == 0) {
+                // lines start one clock apart; a line that has not started keeps Q = 0
+#pragma unroll
+                for (int j = 0; j < DPL; ++j) Q[j] = s >= 0 ? L[j] - m : 0u;
+            } else {
+#pragma unroll
+                for (int j = 0; j < DPL; ++j) Q[j] = L[j] - m;
+            }
+            const size_t o = active ? ((size_t)row * W + x) * kDpad + d0 : trash;
+            store_bytes<DPL>(out + o, L);
         }
-        const uint32_t qm_edge = dpp_mov<kRowShr1>(kInf, Q[DPL - 1]);
-        const uint32_t qp_edge = dpp_mov<kRowShl1>(kInf, Q[0]);
-        uint32_t L[DPL];
-        uint32_t m = 0xFFFFFFFFu;
+        if (c + 1 < nchunks) stage_store(buf ^ 1, staged);
+        __syncthreads();
+    }
+}
+
+template <int DPL, bool WIDE>
+__global__ __launch_bounds__(kBlock) void aggregate_kernel(AggregateArgs a)
+{
+    using Word = typename CensusWord<WIDE>::T;
+    constexpr int kDpad = kLanesPerLine * DPL;
+    constexpr int kTile = kChunk * (kDpad + 2 * kChunk - 1);
+    __shared__ Word tile[2][kTile];
+    int dir = 0;
 #pragma unroll
-        for (int j = 0; j < DPL; ++j) {
-            const uint32_t qm = j > 0 ? Q[j - 1] : qm_edge;
-            const uint32_t qp = j < DPL - 1 ? Q[j + 1] : qp_edge;
-            uint32_t t = min(qm, qp) + p1;
-            t = min(min(Q[j], t), p2);
-            L[j] = C[j] + t;
-            m = min(m, L[j]);
-        }
-        m = row_min(m);
-#pragma unroll
-        for (int j = 0; j < DPL; ++j) Q[j] = L[j] - m;
-        store_bytes<DPL>(out + (row + x) * (size_t)Dpad + d0, L);
+    for (int k = 1; k < 8; ++k)
+        if (k < a.ndirs && (int)blockIdx.x >= a.block_begin[k]) dir = k;
+    const BlockGeom g = block_geometry(a.dx[dir], a.dy[dir], (int)blockIdx.x - a.block_begin[dir], a.W, a.H);
+    uint8_t *out = a.out[dir];
+    if (g.kind == 0) {
+        // horizontal lines are the longest dependency chains of the pass
+        __builtin_amdgcn_s_setprio(2);
+        run_lines<DPL, WIDE, 0>(a, g, out, tile);
+    } else if (g.kind == 1) {
+        run_lines<DPL, WIDE, 1>(a, g, out, tile);
+    } else {
+        run_lines<DPL, WIDE, 2>(a, g, out, tile);
     }
 }
 
@@ -197,6 +368,14 @@ hipError_t launch_agg_dpl(const AggregateArgs &a, bool wide, hipStream_t s)
     return hipGetLastError();
 }
 }  // namespace
+
+int aggregate_blocks(int dx, int dy, int W, int H)
+{
+    if (dy == 0) return (H + kChunk - 1) / kChunk;
+    const int top = (W + kChunk - 1) / kChunk;
+    if (dx == 0) return top;
+    return top + (H - 1 + kChunk - 1) / kChunk;
+}
 
 hipError_t launch_aggregate(const AggregateArgs &a, bool wide, hipStream_t s)
 {

@@ -60,7 +60,7 @@ static Layout layout(const simsense_params *p)
     const size_t npx = (size_t)p->width * p->height;
     const bool wide = census_bits(p->census_w, p->census_h, p->census_mode) > 32;
     l.census = align256(npx * (wide ? 8 : 4));
-    l.paths = align256(npx * padded_disp(p->max_disp));
+    l.paths = align256((npx + 1) * padded_disp(p->max_disp));  // + one spare pixel for idle lanes
     static const int px_bytes[7] = {1, 2, 2, 1, 4, 4, 1};  // dint, S1, S2, dright, dsub, masked, flags
     l.total = 2 * l.census + (size_t)p->num_paths * l.paths;
     for (int i = 0; i < 7; ++i) {
@@ -233,8 +233,7 @@ int simsense_compute_ex(simsense_handle *h, const uint8_t *left, const uint8_t *
         ag.dx[r] = kPathDx[r];
         ag.dy[r] = kPathDy[r];
         ag.out[r] = h->paths[r];
-        const int lines = path_lines(kPathDx[r], kPathDy[r], W, H);
-        ag.block_begin[r + 1] = ag.block_begin[r] + (lines + kLinesPerBlock - 1) / kLinesPerBlock;
+        ag.block_begin[r + 1] = ag.block_begin[r] + aggregate_blocks(kPathDx[r], kPathDy[r], W, H);
     }
     SS_MARK(SIMSENSE_PASS_AGGREGATE, false);
     SS_TRY(launch_aggregate(ag, h->wide, s));
@@ -245,6 +244,7 @@ int simsense_compute_ex(simsense_handle *h, const uint8_t *left, const uint8_t *
     sa.ndirs = h->ndirs;
     sa.W = W; sa.H = H; sa.D = D; sa.Dpad = h->Dpad;
     sa.uniqueness_pct = p.uniqueness_pct; sa.lr_max_diff = p.lr_max_diff; sa.subpixel = p.subpixel;
+    sa.small_values = h->bits + p.p2 <= 127;
     sa.disp_int = h->disp_int; sa.cost_best = h->cost_best; sa.cost_second = h->cost_second;
     sa.disp_right = h->disp_right; sa.disp_sub = h->disp_sub; sa.masked = h->masked; sa.flags = h->flags_pre;
     SS_MARK(SIMSENSE_PASS_SELECT, false);

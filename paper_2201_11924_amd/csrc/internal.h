@@ -24,6 +24,8 @@ int census_bits(int cw, int ch, int mode);
 extern const int kPathDx[8];
 extern const int kPathDy[8];
 int path_lines(int dx, int dy, int W, int H);
+// blocks of 16 lines the aggregation kernel launches for one direction
+int aggregate_blocks(int dx, int dy, int W, int H);
 
 struct AggregateArgs {
     const void *census_l, *census_r;  // uint32 words, or uint64 when bits > 32
@@ -39,6 +41,7 @@ struct SelectArgs {
     int ndirs;
     int W, H, D, Dpad;
     int uniqueness_pct, lr_max_diff, subpixel;
+    int small_values;     // every path value < 128 (bits + P2 <= 127)
     uint8_t *disp_int;    // W*H
     uint16_t *cost_best;  // W*H
     uint16_t *cost_second;

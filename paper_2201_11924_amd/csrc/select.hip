@@ -41,71 +41,119 @@ __device__ __forceinline__ uint32_t row_or(uint32_t v)
     return v;
 }
 
-// adds the dpl path-value bytes at src to S
+constexpr int kSelBlock = 1024;                           // one image row per block
+constexpr int kSelGroups = kSelBlock / kLanesPerLine;     // pixels in flight per row
+
+// the dpl path-value bytes of one direction for this lane, as packed words
 template <int DPL>
-__device__ __forceinline__ void add_bytes(const uint8_t *src, uint32_t (&S)[DPL])
+struct Words {
+    static constexpr int N = (DPL + 3) / 4;
+    uint32_t w[N];
+};
+
+template <int DPL>
+__device__ __forceinline__ void load_words(const uint8_t *src, Words<DPL> &o)
 {
-    if constexpr (DPL % 4 == 0) {
-        uint32_t w[DPL / 4];
-        if constexpr (DPL == 4) {
-            w[0] = *(const uint32_t *)src;
-        } else if constexpr (DPL == 8) {
-            uint2 v = *(const uint2 *)src;
-            w[0] = v.x;
-            w[1] = v.y;
-        } else if constexpr (DPL == 12) {
-            uint2 v = *(const uint2 *)src;
-            w[0] = v.x;
-            w[1] = v.y;
-            w[2] = *(const uint32_t *)(src + 8);
-        } else {
-            uint4 v = *(const uint4 *)src;
-            w[0] = v.x;
-            w[1] = v.y;
-            w[2] = v.z;
-            w[3] = v.w;
-        }
+    if constexpr (DPL == 4) {
+        o.w[0] = *(const uint32_t *)src;
+    } else if constexpr (DPL == 8) {
+        const uint2 v = *(const uint2 *)src;
+        o.w[0] = v.x;
+        o.w[1] = v.y;
+    } else if constexpr (DPL == 12) {
+        const uint2 v = *(const uint2 *)src;
+        o.w[0] = v.x;
+        o.w[1] = v.y;
+        o.w[2] = *(const uint32_t *)(src + 8);
+    } else if constexpr (DPL == 16) {
+        const uint4 v = *(const uint4 *)src;
+        o.w[0] = v.x;
+        o.w[1] = v.y;
+        o.w[2] = v.z;
+        o.w[3] = v.w;
+    } else if constexpr (DPL == 6) {
+        const uint32_t a0 = *(const uint16_t *)src, a1 = *(const uint16_t *)(src + 2),
+                       a2 = *(const uint16_t *)(src + 4);
+        o.w[0] = a0 | (a1 << 16);
+        o.w[1] = a2;
+    } else if constexpr (DPL == 2) {
+        o.w[0] = *(const uint16_t *)src;
+    } else {
+        static_assert(DPL == 1, "unsupported disparities per lane");
+        o.w[0] = *src;
+    }
+}
+
+// S(d) = sum over directions of the path bytes.  Bytes are split into two
+// 16-bit lanes per word (bytes 0,2 and bytes 1,3) and summed there; no lane
+// can carry into the next because a sum of 8 bytes is below 2^16.  When every
+// path value is below 128 (bits + P2 <= 127) two directions are first added as
+// whole words, since no byte of such a sum can carry.
+template <int DPL, int NDIR, bool SMALL>
+__device__ __forceinline__ void sum_paths(const Words<DPL> (&v)[NDIR], uint32_t (&S)[DPL])
+{
+    constexpr int N = Words<DPL>::N;
+    uint32_t lo[N], hi[N];
 #pragma unroll
-        for (int k = 0; k < DPL / 4; ++k)
+    for (int k = 0; k < N; ++k) lo[k] = hi[k] = 0;
+    if constexpr (SMALL) {
 #pragma unroll
-            for (int b = 0; b < 4; ++b) S[4 * k + b] += (w[k] >> (8 * b)) & 0xFF;
-    } else if constexpr (DPL % 2 == 0) {
+        for (int r = 0; r < NDIR; r += 2)
 #pragma unroll
-        for (int k = 0; k < DPL / 2; ++k) {
-            uint32_t h = *(const uint16_t *)(src + 2 * k);
-            S[2 * k] += h & 0xFF;
-            S[2 * k + 1] += h >> 8;
-        }
+            for (int k = 0; k < N; ++k) {
+                const uint32_t w = v[r].w[k] + v[r + 1].w[k];
+                lo[k] += w & 0x00FF00FFu;
+                hi[k] += (w >> 8) & 0x00FF00FFu;
+            }
     } else {
 #pragma unroll
-        for (int k = 0; k < DPL; ++k) S[k] += src[k];
+        for (int r = 0; r < NDIR; ++r)
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                lo[k] += v[r].w[k] & 0x00FF00FFu;
+                hi[k] += (v[r].w[k] >> 8) & 0x00FF00FFu;
+            }
+    }
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) {
+        const int k = j / 4, b = j % 4;
+        const uint32_t src = (b & 1) ? hi[k] : lo[k];
+        S[j] = (b & 2) ? (src >> 16) : (src & 0xFFFFu);
     }
 }
 
 }  // namespace
 
-template <int DPL>
-__global__ __launch_bounds__(kBlock) void select_kernel(SelectArgs a)
+template <int DPL, int NDIR, bool SMALL>
+__global__ __launch_bounds__(kSelBlock) void select_kernel(SelectArgs a)
 {
     extern __shared__ uint32_t smem[];
     const int W = a.W, D = a.D, Dpad = a.Dpad;
-    uint32_t *keyR = smem;                     // W
-    float *dsub_row = (float *)(keyR + W);     // W
+    uint32_t *keyR = smem;                          // W
+    float *dsub_row = (float *)(keyR + W);          // W
     uint8_t *dint_row = (uint8_t *)(dsub_row + W);  // W
-    uint8_t *uniq_row = dint_row + W;          // W
+    uint8_t *uniq_row = dint_row + W;               // W
     const int y = blockIdx.x;
     const size_t row = (size_t)y * W;
-    for (int x = threadIdx.x; x < W; x += kBlock) keyR[x] = 0xFFFFFFFFu;
+    for (int x = threadIdx.x; x < W; x += kSelBlock) keyR[x] = 0xFFFFFFFFu;
     __syncthreads();
 
     const int lane = threadIdx.x % kLanesPerLine, group = threadIdx.x / kLanesPerLine;
     const int d0 = lane * DPL;
-    for (int x = group; x < W; x += kLinesPerBlock) {
-        const size_t pix = row + x;
-        uint32_t S[DPL];
+    Words<DPL> cur[NDIR], nxt[NDIR];
+    if (group < W) {
 #pragma unroll
-        for (int j = 0; j < DPL; ++j) S[j] = 0;
-        for (int r = 0; r < a.ndirs; ++r) add_bytes<DPL>(a.paths[r] + pix * Dpad + d0, S);
+        for (int r = 0; r < NDIR; ++r) load_words<DPL>(a.paths[r] + (row + group) * Dpad + d0, cur[r]);
+    }
+    for (int x = group; x < W; x += kSelGroups) {
+        const size_t pix = row + x;
+        const int xn = x + kSelGroups;
+        if (xn < W) {
+#pragma unroll
+            for (int r = 0; r < NDIR; ++r) load_words<DPL>(a.paths[r] + (row + xn) * Dpad + d0, nxt[r]);
+        }
+        uint32_t S[DPL];
+        sum_paths<DPL, NDIR, SMALL>(cur, S);
 
         uint32_t key[DPL];
         uint32_t kmin = 0xFFFFFFFFu;
@@ -145,10 +193,12 @@ __global__ __launch_bounds__(kBlock) void select_kernel(SelectArgs a)
             dsub_row[x] = ds;
             uniq_row[x] = uniq;
         }
+#pragma unroll
+        for (int r = 0; r < NDIR; ++r) cur[r] = nxt[r];
     }
     __syncthreads();
     const int lr = a.lr_max_diff;
-    for (int x = threadIdx.x; x < W; x += kBlock) {
+    for (int x = threadIdx.x; x < W; x += kSelBlock) {
         const int d = dint_row[x];
         const int xr = x - d;
         bool lr_ok = true;
@@ -160,15 +210,36 @@ __global__ __launch_bounds__(kBlock) void select_kernel(SelectArgs a)
     }
 }
 
+namespace {
+template <int DPL, int NDIR>
+void launch_sel3(const SelectArgs &a, hipStream_t s)
+{
+    dim3 grid(a.H), block(kSelBlock);
+    const size_t lds = (size_t)a.W * 10;
+    if (a.small_values)
+        hipLaunchKernelGGL((select_kernel<DPL, NDIR, true>), grid, block, lds, s, a);
+    else
+        hipLaunchKernelGGL((select_kernel<DPL, NDIR, false>), grid, block, lds, s, a);
+}
+template <int DPL>
+void launch_sel2(const SelectArgs &a, hipStream_t s)
+{
+    if (a.ndirs == 2) launch_sel3<DPL, 2>(a, s);
+    else if (a.ndirs == 4) launch_sel3<DPL, 4>(a, s);
+    else launch_sel3<DPL, 8>(a, s);
+}
+}  // namespace
+
 hipError_t launch_select(const SelectArgs &a, hipStream_t s)
 {
-    dim3 grid(a.H), block(kBlock);
-    size_t lds = (size_t)a.W * 10;
     switch (a.Dpad / kLanesPerLine) {
-#define SS_CASE(N) \
-    case N: hipLaunchKernelGGL(select_kernel<N>, grid, block, lds, s, a); break;
-        SS_CASE(1) SS_CASE(2) SS_CASE(4) SS_CASE(6) SS_CASE(8) SS_CASE(12) SS_CASE(16)
-#undef SS_CASE
+    case 1: launch_sel2<1>(a, s); break;
+    case 2: launch_sel2<2>(a, s); break;
+    case 4: launch_sel2<4>(a, s); break;
+    case 6: launch_sel2<6>(a, s); break;
+    case 8: launch_sel2<8>(a, s); break;
+    case 12: launch_sel2<12>(a, s); break;
+    case 16: launch_sel2<16>(a, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
