@@ -67,6 +67,51 @@ __device__ __forceinline__ uint32_t row_min(uint32_t v)
     return v;
 }
 
+constexpr int kWaveShl1 = 0x130, kWaveShr1 = 0x138, kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+
+// Cross-lane pieces of a line that spans LPL lanes (16: one DPP row, 32: half a
+// wave, 64: the whole wave).  Lanes hold consecutive disparity blocks.
+template <int LPL>
+struct LineOps {
+    // value of the previous lane (lane 0 of the line gets kInf)
+    static __device__ __forceinline__ uint32_t from_prev(uint32_t v, bool first)
+    {
+        if constexpr (LPL == 16) {
+            return dpp_mov<kRowShr1>(kInf, v);
+        } else {
+            const uint32_t r = dpp_mov<kWaveShr1>(kInf, v);
+            return LPL == 32 && first ? kInf : r;
+        }
+    }
+    // value of the next lane (the line's last lane gets kInf)
+    static __device__ __forceinline__ uint32_t from_next(uint32_t v, bool last)
+    {
+        if constexpr (LPL == 16) {
+            return dpp_mov<kRowShl1>(kInf, v);
+        } else {
+            const uint32_t r = dpp_mov<kWaveShl1>(kInf, v);
+            return LPL == 32 && last ? kInf : r;
+        }
+    }
+    // minimum over the line's lanes, in every lane of the line
+    static __device__ __forceinline__ uint32_t line_min(uint32_t v)
+    {
+        v = row_min(v);
+        if constexpr (LPL == 16) {
+            return v;
+        } else if constexpr (LPL == 32) {
+            // rows 1 and 3 take the minimum with lane 15 of the row before them
+            v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, kRowBcast15, 0xA, 0xF, false));
+            const uint32_t lo = __builtin_amdgcn_readlane(v, 31), hi = __builtin_amdgcn_readlane(v, 63);
+            return (threadIdx.x & 32) ? hi : lo;
+        } else {
+            v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, kRowBcast15, 0xA, 0xF, false));
+            v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, kRowBcast31, 0xC, 0xF, false));
+            return __builtin_amdgcn_readlane(v, 63);
+        }
+    }
+};
+
 template <bool WIDE>
 struct CensusWord;
 template <>
@@ -130,7 +175,7 @@ struct BlockGeom {
     int nvalid;  // lines of the block that exist
 };
 
-__device__ __forceinline__ BlockGeom block_geometry(int dx, int dy, int blk, int W, int H)
+__device__ __forceinline__ BlockGeom block_geometry(int dx, int dy, int blk, int W, int H, int hlines)
 {
     BlockGeom g{};
     g.dx = dx;
@@ -139,10 +184,10 @@ __device__ __forceinline__ BlockGeom block_geometry(int dx, int dy, int blk, int
     g.xe = dx > 0 ? 0 : W - 1;
     if (dy == 0) {
         g.kind = 0;
-        g.r0 = blk * kChunk;
+        g.r0 = blk * hlines;
         g.xs = dx > 0 ? 0 : W - 1;
         g.clocks = W;
-        g.nvalid = min(kChunk, H - g.r0);
+        g.nvalid = min(hlines, H - g.r0);
     } else {
         const int top_blocks = (W + kChunk - 1) / kChunk;
         if (dx == 0 || blk < top_blocks) {
@@ -183,22 +228,28 @@ __device__ __forceinline__ void window_at(const BlockGeom &g, int t, int &row, i
 
 }  // namespace
 
-// One block's scanlines, specialised by line kind (see BlockGeom).  The output
-// buffer holds one spare pixel after the image: lanes of lines that have ended
-// (or not started yet) store there, so every step issues the same unconditional
-// store and the loop carries no branch.
-template <int DPL, bool WIDE, int KIND>
+// One block's scanlines, specialised by line kind (see BlockGeom).  LPL lanes
+// hold one line, DPL disparities each (LPL * DPL = Dpad).  The output buffer
+// holds one spare pixel after the image: lanes of lines that have ended (or not
+// started yet) store there, so every step issues the same unconditional store.
+template <int DPL, int LPL, bool WIDE, int KIND, int TILE>
 __device__ __forceinline__ void run_lines(const AggregateArgs &a, const BlockGeom &g, uint8_t *__restrict__ out,
-                                          typename CensusWord<WIDE>::T (*tile)[kLinesPerBlock * (kLanesPerLine * DPL + 2 * kChunk - 1)])
+                                          typename CensusWord<WIDE>::T (*tile)[TILE])
 {
     using CW = CensusWord<WIDE>;
+    using LO = LineOps<LPL>;
     using Word = typename CW::T;
-    constexpr int kDpad = kLanesPerLine * DPL;
-    constexpr int kSlot = kDpad + 2 * kChunk - 1;  // cR window (Dpad + 15) then cL window (16)
-    constexpr int kTile = kChunk * kSlot;
+    constexpr int kDpad = LPL * DPL;
+    constexpr int kLines = kBlock / LPL;                 // lines per block
+    constexpr int kSlots = KIND == 0 ? kLines : kChunk;  // tile slots: lines (kind 0) or clocks
+    constexpr int kSlot = kDpad + 2 * kChunk - 1;        // cR window (Dpad + 15) then cL window (16)
+    constexpr int kTile = kSlots * kSlot;
     constexpr int kPerThread = (kTile + kBlock - 1) / kBlock;
+    static_assert(KIND == 0 || LPL == kLanesPerLine, "row-sharing kinds use one DPP row per line");
+    static_assert(kTile <= TILE, "tile too small");
     const int W = a.W, H = a.H, D = a.D;
-    const int lane = threadIdx.x % kLanesPerLine, li = threadIdx.x / kLanesPerLine;
+    const int lane = threadIdx.x % LPL, li = threadIdx.x / LPL;
+    const bool first = lane == 0, last = lane == LPL - 1;
     const int d0 = lane * DPL;
     const Word *__restrict__ cl = (const Word *)a.census_l;
     const Word *__restrict__ cr = (const Word *)a.census_r;
@@ -256,6 +307,23 @@ __device__ __forceinline__ void run_lines(const AggregateArgs &a, const BlockGeo
             if (q < kTile) tile[buf][q] = v[k];
         }
     };
+    // lane's view of clock c0 + k: pixel, tile slot and window
+    auto locate = [&](int c0, int k, int &x, int &row, int &xm, int &slot) {
+        const int t = c0 + k;
+        slot = KIND == 0 ? li : k;
+        slot_window(c0, slot, row, xm);
+        if (KIND == 0) x = g.xs + t * g.dx;
+        else if (KIND == 1) x = xm + li;
+        else x = xm + (g.dx > 0 ? kChunk - 1 - li : li);
+    };
+    // census words of one clock: cL(x) and cR(x - d) for d = d0 + DPL - 1 .. d0
+    auto fetch = [&](int buf, int slot, int xo, Word &wl, Word(&wr)[DPL]) {
+        const Word *sl = &tile[buf][slot * kSlot];
+        wl = sl[kDpad + kChunk - 1 + xo];
+        const Word *p = sl + (xo + kDpad - d0 - DPL);
+#pragma unroll
+        for (int j = 0; j < DPL; ++j) wr[j] = p[j];
+    };
 
     uint32_t Q[DPL];
 #pragma unroll
@@ -271,24 +339,31 @@ __device__ __forceinline__ void run_lines(const AggregateArgs &a, const BlockGeo
         const int buf = c & 1;
         const int c0 = c * kChunk;
         if (c + 1 < nchunks) stage_load(c0 + kChunk, staged);
+        Word wl_n, wr_n[DPL];
+        {
+            int x, row, xm, slot;
+            locate(c0, 0, x, row, xm, slot);
+            fetch(buf, slot, x - xm, wl_n, wr_n);
+        }
 #pragma unroll
         for (int k = 0; k < kChunk; ++k) {
             const int t = c0 + k;
             const int s = t - skew;
-            int x, row, xm;
-            const int slot = KIND == 0 ? li : k;
-            slot_window(c0, slot, row, xm);
-            if (KIND == 0) x = g.xs + t * g.dx;
-            else if (KIND == 1) x = xm + li;
-            else x = xm + (g.dx > 0 ? kChunk - 1 - li : li);
+            int x, row, xm, slot;
+            locate(c0, k, x, row, xm, slot);
+            const Word wl = wl_n;
+            Word wr[DPL];
+#pragma unroll
+            for (int j = 0; j < DPL; ++j) wr[j] = wr_n[j];
+            if (k + 1 < kChunk) {
+                // next clock's census words are read while this clock computes
+                int xn, rown, xmn, slotn;
+                locate(c0, k + 1, xn, rown, xmn, slotn);
+                fetch(buf, slotn, xn - xmn, wl_n, wr_n);
+            }
             const bool active = s >= 0 && s < len;
-            const Word *sl = &tile[buf][slot * kSlot];
-            const int xo = x - xm;  // 0..15 for every lane
-            const Word wl = sl[kDpad + kChunk - 1 + xo];
-            // words for d = d0 + DPL - 1 .. d0 sit at increasing addresses from here
-            const Word *wr = sl + (xo + kDpad - d0 - DPL);
-            const uint32_t qm_edge = dpp_mov<kRowShr1>(kInf, Q[DPL - 1]);
-            const uint32_t qp_edge = dpp_mov<kRowShl1>(kInf, Q[0]);
+            const uint32_t qm_edge = LO::from_prev(Q[DPL - 1], first);
+            const uint32_t qp_edge = LO::from_next(Q[0], last);
             uint32_t L[DPL];
             uint32_t m = 0xFFFFFFFFu;
             // the block's leftmost column decides whether any lane sees x - d < 0
@@ -315,7 +390,7 @@ __device__ __forceinline__ void run_lines(const AggregateArgs &a, const BlockGeo
                     m = min(m, L[j]);
                 }
             }
-            m = row_min(m);
+            m = LO::line_min(m);
             if (KIND == 2 && c == 0) {
                 // lines start one clock apart; a line that has not started keeps Q = 0
 #pragma unroll
@@ -337,22 +412,25 @@ __global__ __launch_bounds__(kBlock) void aggregate_kernel(AggregateArgs a)
 {
     using Word = typename CensusWord<WIDE>::T;
     constexpr int kDpad = kLanesPerLine * DPL;
+    constexpr int kHL = horizontal_lanes(kDpad);
     constexpr int kTile = kChunk * (kDpad + 2 * kChunk - 1);
     __shared__ Word tile[2][kTile];
     int dir = 0;
 #pragma unroll
     for (int k = 1; k < 8; ++k)
         if (k < a.ndirs && (int)blockIdx.x >= a.block_begin[k]) dir = k;
-    const BlockGeom g = block_geometry(a.dx[dir], a.dy[dir], (int)blockIdx.x - a.block_begin[dir], a.W, a.H);
+    const BlockGeom g = block_geometry(a.dx[dir], a.dy[dir], (int)blockIdx.x - a.block_begin[dir], a.W, a.H,
+                                       kBlock / kHL);
     uint8_t *out = a.out[dir];
     if (g.kind == 0) {
-        // horizontal lines are the longest dependency chains of the pass
+        // horizontal lines are the longest dependency chains of the pass: more
+        // lanes per line to shorten each step, and issue priority
         __builtin_amdgcn_s_setprio(2);
-        run_lines<DPL, WIDE, 0>(a, g, out, tile);
+        run_lines<kDpad / kHL, kHL, WIDE, 0, kTile>(a, g, out, tile);
     } else if (g.kind == 1) {
-        run_lines<DPL, WIDE, 1>(a, g, out, tile);
+        run_lines<DPL, kLanesPerLine, WIDE, 1, kTile>(a, g, out, tile);
     } else {
-        run_lines<DPL, WIDE, 2>(a, g, out, tile);
+        run_lines<DPL, kLanesPerLine, WIDE, 2, kTile>(a, g, out, tile);
     }
 }
 
@@ -369,9 +447,12 @@ hipError_t launch_agg_dpl(const AggregateArgs &a, bool wide, hipStream_t s)
 }
 }  // namespace
 
-int aggregate_blocks(int dx, int dy, int W, int H)
+int aggregate_blocks(int dx, int dy, int W, int H, int dpad)
 {
-    if (dy == 0) return (H + kChunk - 1) / kChunk;
+    if (dy == 0) {
+        const int lines = kBlock / horizontal_lanes(dpad);
+        return (H + lines - 1) / lines;
+    }
     const int top = (W + kChunk - 1) / kChunk;
     if (dx == 0) return top;
     return top + (H - 1 + kChunk - 1) / kChunk;

@@ -233,7 +233,7 @@ int simsense_compute_ex(simsense_handle *h, const uint8_t *left, const uint8_t *
         ag.dx[r] = kPathDx[r];
         ag.dy[r] = kPathDy[r];
         ag.out[r] = h->paths[r];
-        ag.block_begin[r + 1] = ag.block_begin[r] + aggregate_blocks(kPathDx[r], kPathDy[r], W, H);
+        ag.block_begin[r + 1] = ag.block_begin[r] + aggregate_blocks(kPathDx[r], kPathDy[r], W, H, h->Dpad);
     }
     SS_MARK(SIMSENSE_PASS_AGGREGATE, false);
     SS_TRY(launch_aggregate(ag, h->wide, s));

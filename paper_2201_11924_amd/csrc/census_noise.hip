@@ -62,13 +62,15 @@ __global__ __launch_bounds__(256) void census_kernel(const uint8_t *__restrict__
     Word word = 0;
     int k = 0;
     if (mode == 0) {
-        const int half = (cw * ch - 1) / 2;
-        for (int i = 0; i < half; ++i) {
-            int oy = i / cw - rh, ox = i % cw - rw;
-            int a = tile[(cy + oy) * tw + cx + ox];
-            int b = tile[(cy - oy) * tw + cx - ox];
-            word |= (Word)(a > b) << k;
-            ++k;
+        // offsets before the centre: every row above it, then the left half of its row
+        for (int oy = -rh; oy <= 0; ++oy) {
+            const int oxe = oy < 0 ? rw : -1;
+            const uint8_t *pa = &tile[(cy + oy) * tw + cx];
+            const uint8_t *pb = &tile[(cy - oy) * tw + cx];
+            for (int ox = -rw; ox <= oxe; ++ox) {
+                word |= (Word)(pa[ox] > pb[-ox]) << k;
+                ++k;
+            }
         }
     } else {
         const int c = tile[cy * tw + cx];

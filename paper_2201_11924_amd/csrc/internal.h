@@ -24,8 +24,11 @@ int census_bits(int cw, int ch, int mode);
 extern const int kPathDx[8];
 extern const int kPathDy[8];
 int path_lines(int dx, int dy, int W, int H);
-// blocks of 16 lines the aggregation kernel launches for one direction
-int aggregate_blocks(int dx, int dy, int W, int H);
+// Lanes per horizontal line: horizontal lines are the longest chains of the
+// aggregation, so they are spread over more lanes (fewer instructions per step).
+constexpr int horizontal_lanes(int dpad) { return dpad % 64 == 0 ? 64 : (dpad % 32 == 0 ? 32 : 16); }
+// blocks the aggregation kernel launches for one direction
+int aggregate_blocks(int dx, int dy, int W, int H, int dpad);
 
 struct AggregateArgs {
     const void *census_l, *census_r;  // uint32 words, or uint64 when bits > 32

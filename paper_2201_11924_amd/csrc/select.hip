@@ -41,7 +41,7 @@ __device__ __forceinline__ uint32_t row_or(uint32_t v)
     return v;
 }
 
-constexpr int kSelBlock = 1024;                           // one image row per block
+constexpr int kSelBlock = 512;                            // one image row per block
 constexpr int kSelGroups = kSelBlock / kLanesPerLine;     // pixels in flight per row
 
 // the dpl path-value bytes of one direction for this lane, as packed words
