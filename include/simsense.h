@@ -92,6 +92,9 @@ typedef struct simsense_outputs {
     float *disp_sub;     /* fp32 sub-pixel disparity before masking and median */
     uint64_t *census_left, *census_right; /* census words, bit k = k-th window comparison */
     uint16_t *volume;    /* summed path costs S, width*height*max_disp, d fastest */
+    uint16_t *features;  /* input of the learned surrogate: bf16, 8 channels per pixel (pixel-major):
+                            IR / 255, S1 / Smax, S2 / Smax (1 where no S2), d* / D, then 4 zeros;
+                            Smax = num_paths * (census bits + p2) */
 } simsense_outputs;
 
 /* Allocates a handle and its device scratch for one parameter set on the
@@ -139,6 +142,68 @@ int simsense_census(const simsense_params *params, const uint8_t *img, int32_t p
 #define SIMSENSE_NUM_PASSES 4
 int simsense_profile_enable(simsense_handle *h, int enable);
 int simsense_profile_read(simsense_handle *h, double *ms, int32_t *calls, int32_t n);
+
+/* ------------------------------------------------------------------------
+ * Learned surrogate (a project addition, not in the paper): a 4-layer 3x3
+ * convolutional net, 4 -> 32 -> 32 -> 32 -> 2 channels with ReLU after the first
+ * three and zero padding, BF16 weights and activations with FP32 accumulation,
+ * that reads the features of a 2-path (horizontal) SGM result (see
+ * simsense_outputs.features) and predicts a disparity residual (channel 0) and a
+ * validity logit (channel 1).  It stands in for the six non-horizontal paths of
+ * the paper's aggregation (Sec. VI-D); 8-path SGM stays the reference.
+ *
+ * Parameters are a flat fp32 vector of simsense_net_num_params() values, layer
+ * by layer: weights [ky][kx][ci][co] (out(y,x) += in(y+ky-1, x+kx-1, ci) * w),
+ * then biases [co].  Training minimises the mean absolute residual error over
+ * pixels where the 8-path result is valid plus the mean binary cross-entropy
+ * of the logit against that validity, with Adam (beta1 0.9, beta2 0.999, eps 1e-8).
+ * ---------------------------------------------------------------------- */
+typedef struct simsense_net simsense_net; /* opaque */
+
+int64_t simsense_net_num_params(void);
+
+/* Allocates a net for up to `max_pixels` = batch * height * width pixels per call
+ * (about 360 bytes of device memory per pixel) with He-uniform weights drawn from
+ * `seed` and zero biases; Adam state zero.  Synchronous. */
+int simsense_net_create(int64_t max_pixels, uint64_t seed, simsense_net **out);
+int simsense_net_destroy(simsense_net *net);
+
+/* HOST buffers of `count` = simsense_net_num_params() floats.  get waits for the
+ * net's last stream; NULL buffers are skipped.  set copies parameters (and Adam
+ * moments, zero when NULL) and the step counter, then rebuilds the bf16 layouts;
+ * synchronous.  Together they checkpoint and resume training exactly. */
+int simsense_net_get_state(simsense_net *net, float *params, float *m, float *v, int64_t count, int64_t *step);
+int simsense_net_set_state(simsense_net *net, const float *params, const float *m, const float *v,
+                           int64_t count, int64_t step);
+/* HOST buffer: the gradient computed by the last training step. */
+int simsense_net_get_grads(simsense_net *net, float *grads, int64_t count);
+
+/* Forward pass.  `features`: bf16 [batch][height][width][8] (device); `out`: fp32
+ * [batch][height][width][2] (device): residual, logit. */
+int simsense_net_forward(simsense_net *net, const uint16_t *features, int32_t batch, int32_t height,
+                         int32_t width, float *out, void *stream);
+
+/* One Adam step on a batch.  `target_residual` fp32 and `target_valid` uint8 (0/1)
+ * are [batch][height][width] (device).  `loss` (device, nullable) receives
+ * {total, l1, bce} of the forward pass before the update. */
+int simsense_net_train_step(simsense_net *net, const uint16_t *features, const float *target_residual,
+                            const uint8_t *target_valid, int32_t batch, int32_t height, int32_t width,
+                            float lr, float *loss, void *stream);
+
+/* Training targets from an 8-path and a 2-path result of the same pair (device,
+ * `count` pixels): target_residual = d8_sub - d2_sub, target_valid = 1 where the
+ * 8-path flags have the uniqueness, LR and nonzero bits. */
+int simsense_net_targets(const float *d8_sub, const uint8_t *flags8, const float *d2_sub, float *target_residual,
+                         uint8_t *target_valid, int64_t count, void *stream);
+
+/* The learned depth path: matching with the handle's parameters (normally
+ * num_paths = 2), features, the net, then disparity = d2_sub + residual where the
+ * logit is positive and the sum is positive (else invalid), then the handle's
+ * median and depth.  Writes the outputs requested in `out` that this path
+ * produces: depth, disp, flags, disp_sub (the 2-path sub-pixel map), disp_int,
+ * features.  width * height must not exceed the net's max_pixels. */
+int simsense_learned_compute(simsense_handle *h, simsense_net *net, const uint8_t *left, const uint8_t *right,
+                             int32_t pitch, const simsense_outputs *out, void *stream);
 
 /* Human-readable name of a status code (static storage). */
 const char *simsense_strerror(int status);

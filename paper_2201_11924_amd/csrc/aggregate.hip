@@ -158,6 +158,21 @@ __device__ __forceinline__ void store_bytes(uint8_t *dst, const uint32_t (&L)[DP
     }
 }
 
+// s_waitcnt immediate that waits for vmcnt <= n and leaves the other counters
+// alone (GFX9 encoding: vmcnt[3:0] | expcnt[6:4] | lgkmcnt[11:8] | vmcnt_hi[15:14])
+__host__ __device__ constexpr int vmcnt_encoding(int n)
+{
+    // counts above the 6-bit maximum wait for more than needed, which is safe
+    return n > 63 ? vmcnt_encoding(63) : (n & 0xF) | (0x7 << 4) | (0xF << 8) | (((n >> 4) & 0x3) << 14);
+}
+
+// global store instructions store_bytes issues per step
+template <int DPL>
+__host__ __device__ constexpr int store_ops()
+{
+    return DPL % 4 == 0 ? (DPL == 12 ? 2 : 1) : (DPL % 2 == 0 ? DPL / 2 : DPL);
+}
+
 // Geometry of one block of 16 lines of one direction.
 //  kind 0: horizontal; the 16 lines are rows r0..r0+15 and every line is at
 //          column xs + t*dx at clock t;
@@ -228,97 +243,108 @@ __device__ __forceinline__ void window_at(const BlockGeom &g, int t, int &row, i
 
 }  // namespace
 
-// One block's scanlines, specialised by line kind (see BlockGeom).  LPL lanes
-// hold one line, DPL disparities each (LPL * DPL = Dpad).  The output buffer
-// holds one spare pixel after the image: lanes of lines that have ended (or not
-// started yet) store there, so every step issues the same unconditional store.
-template <int DPL, int LPL, bool WIDE, int KIND, int TILE>
+// One block's scanlines.  HORIZ selects the horizontal layout (kind 0);
+// otherwise the block is of kind 1 or 2, whose lines share one image row per
+// clock: row(t) = row0 + t*dy, leftmost column xm(t) = xm0 + t*dx, lane column
+// xm(t) + xlane.  LPL lanes hold one line, DPL disparities each (LPL * DPL = Dpad).
+//
+// Census tiles move global -> LDS with direct-to-LDS loads into a ring of three
+// tile buffers, two chunks ahead of the chunk being computed; every lane of a
+// wave writes 4 consecutive bytes, so the tile is filled as a flat array of
+// dwords (two per word when census words are 64-bit).
+//
+// A kind-2 line that has not started yet (clock < its skew) is fed zero cost:
+// from Q = 0 the recurrence then yields L = 0 and m = 0, so Q stays 0 until the
+// line's first pixel, exactly the state a line starts from.  Lanes of lines that
+// have ended (or not started) store into one spare pixel after the image, so
+// every step issues the same unconditional store.
+template <int DPL, int LPL, bool WIDE, bool HORIZ, int TILE>
 __device__ __forceinline__ void run_lines(const AggregateArgs &a, const BlockGeom &g, uint8_t *__restrict__ out,
-                                          typename CensusWord<WIDE>::T (*tile)[TILE])
+                                          uint32_t (*tile)[TILE])
 {
     using CW = CensusWord<WIDE>;
     using LO = LineOps<LPL>;
     using Word = typename CW::T;
+    constexpr int kWordDw = WIDE ? 2 : 1;                // dwords per census word
     constexpr int kDpad = LPL * DPL;
     constexpr int kLines = kBlock / LPL;                 // lines per block
-    constexpr int kSlots = KIND == 0 ? kLines : kChunk;  // tile slots: lines (kind 0) or clocks
+    constexpr int kSlots = HORIZ ? kLines : kChunk;      // tile slots: lines or clocks
     constexpr int kSlot = kDpad + 2 * kChunk - 1;        // cR window (Dpad + 15) then cL window (16)
-    constexpr int kTile = kSlots * kSlot;
-    constexpr int kPerThread = (kTile + kBlock - 1) / kBlock;
-    static_assert(KIND == 0 || LPL == kLanesPerLine, "row-sharing kinds use one DPP row per line");
-    static_assert(kTile <= TILE, "tile too small");
+    constexpr int kTileDw = kSlots * kSlot * kWordDw;
+    constexpr int kLoads = (kTileDw + kBlock - 1) / kBlock;
+    static_assert(HORIZ || LPL == kLanesPerLine, "row-sharing lines use one DPP row per line");
+    static_assert(kLoads * kBlock <= TILE, "tile too small");
     const int W = a.W, H = a.H, D = a.D;
     const int lane = threadIdx.x % LPL, li = threadIdx.x / LPL;
     const bool first = lane == 0, last = lane == LPL - 1;
     const int d0 = lane * DPL;
-    const Word *__restrict__ cl = (const Word *)a.census_l;
-    const Word *__restrict__ cr = (const Word *)a.census_r;
+    const uint32_t *__restrict__ cl = (const uint32_t *)a.census_l;
+    const uint32_t *__restrict__ cr = (const uint32_t *)a.census_r;
     const uint32_t p1 = a.p1, p2 = a.p2, bits = a.bits;
     const bool padded = D < kDpad;
     const size_t trash = (size_t)W * H * kDpad + d0;
 
-    int len = 0, skew = 0;
-    if (li < g.nvalid) {
-        if (KIND == 0) {
-            len = W;
-        } else if (KIND == 1) {
+    // per-block line layout
+    int row0 = 0, xm0 = 0, xlane = 0, len = 0, skew = 0;
+    if (HORIZ) {
+        if (li < g.nvalid) len = W;
+    } else if (g.kind == 1) {
+        row0 = g.ye;
+        xm0 = g.g0;
+        xlane = li;
+        if (li < g.nvalid) {
             const int x0 = g.g0 + li;
             len = g.dx == 0 ? H : min(g.dx > 0 ? W - x0 : x0 + 1, H);
-        } else {
-            skew = li;
-            len = min(W, H - g.j0 - li - 1);
         }
+    } else {
+        row0 = g.ye + g.dy * (g.j0 + 1);
+        xm0 = g.dx > 0 ? g.xe - (kChunk - 1) : g.xe;
+        xlane = g.dx > 0 ? kChunk - 1 - li : li;
+        skew = li;
+        if (li < g.nvalid) len = min(W, H - g.j0 - li - 1);
     }
+    const bool skewed = !HORIZ && g.kind == 2;
 
-    // row and leftmost column of the 16-column window of tile slot `slot`
+    // row and leftmost column of the 16-column window of tile slot `slot` of the
+    // chunk that starts at clock c0
     auto slot_window = [&](int c0, int slot, int &row, int &xm) {
-        if (KIND == 0) {
+        if (HORIZ) {
             row = g.r0 + slot;
             const int xc = g.xs + c0 * g.dx;
             xm = g.dx > 0 ? xc : xc - (kChunk - 1);
-        } else if (KIND == 1) {
-            row = g.ye + (c0 + slot) * g.dy;
-            xm = g.g0 + (c0 + slot) * g.dx;
         } else {
-            const int t = c0 + slot;
-            row = g.ye + g.dy * (g.j0 + 1 + t);
-            xm = g.dx > 0 ? g.xe + t - (kChunk - 1) : g.xe - t;
+            row = row0 + (c0 + slot) * g.dy;
+            xm = xm0 + (c0 + slot) * g.dx;
         }
     };
-    auto stage_load = [&](int c0, Word(&v)[kPerThread]) {
+    // direct-to-LDS loads of the chunk starting at clock c0 into ring buffer buf
+    auto stage = [&](int c0, int buf) {
 #pragma unroll
-        for (int k = 0; k < kPerThread; ++k) {
-            const int q = threadIdx.x + k * kBlock;
-            const int slot = q / kSlot, idx = q - slot * kSlot;
+        for (int k = 0; k < kLoads; ++k) {
+            const int e = threadIdx.x + k * kBlock;  // dword of the tile
+            const int q = e / kWordDw, h = e - q * kWordDw;
+            const int qc = q < kSlots * kSlot ? q : kSlots * kSlot - 1;
+            const int slot = qc / kSlot, idx = qc - slot * kSlot;
             int row, xm;
             slot_window(c0, slot, row, xm);
             const bool is_left = idx >= kDpad + kChunk - 1;
             int col = is_left ? xm + idx - (kDpad + kChunk - 1) : xm - kDpad + 1 + idx;
             row = min(max(row, 0), H - 1);
             col = min(max(col, 0), W - 1);
-            const Word *src = is_left ? cl : cr;
-            v[k] = q < kTile ? src[(size_t)row * W + col] : Word(0);
+            const uint32_t *src = (is_left ? cl : cr) + ((size_t)row * W + col) * kWordDw + h;
+            __builtin_amdgcn_global_load_lds(src, &tile[buf][k * kBlock + (threadIdx.x & ~63)], 4, 0, 0);
         }
     };
-    auto stage_store = [&](int buf, const Word(&v)[kPerThread]) {
-#pragma unroll
-        for (int k = 0; k < kPerThread; ++k) {
-            const int q = threadIdx.x + k * kBlock;
-            if (q < kTile) tile[buf][q] = v[k];
-        }
-    };
-    // lane's view of clock c0 + k: pixel, tile slot and window
+    // lane's pixel, tile slot and window at clock c0 + k
     auto locate = [&](int c0, int k, int &x, int &row, int &xm, int &slot) {
         const int t = c0 + k;
-        slot = KIND == 0 ? li : k;
+        slot = HORIZ ? li : k;
         slot_window(c0, slot, row, xm);
-        if (KIND == 0) x = g.xs + t * g.dx;
-        else if (KIND == 1) x = xm + li;
-        else x = xm + (g.dx > 0 ? kChunk - 1 - li : li);
+        x = HORIZ ? g.xs + t * g.dx : xm + xlane;
     };
     // census words of one clock: cL(x) and cR(x - d) for d = d0 + DPL - 1 .. d0
     auto fetch = [&](int buf, int slot, int xo, Word &wl, Word(&wr)[DPL]) {
-        const Word *sl = &tile[buf][slot * kSlot];
+        const Word *sl = (const Word *)&tile[buf][0] + slot * kSlot;
         wl = sl[kDpad + kChunk - 1 + xo];
         const Word *p = sl + (xo + kDpad - d0 - DPL);
 #pragma unroll
@@ -329,16 +355,19 @@ __device__ __forceinline__ void run_lines(const AggregateArgs &a, const BlockGeo
 #pragma unroll
     for (int j = 0; j < DPL; ++j) Q[j] = 0;
 
-    Word staged[kPerThread];
-    stage_load(0, staged);
-    stage_store(0, staged);
+    const int nchunks = (g.clocks + kChunk - 1) / kChunk;
+    stage(0, 0);
+    if (nchunks > 1) stage(kChunk, 1);
+    // chunk 0 must be in LDS: at most chunk 1's loads may still be in flight
+    if (nchunks > 1) __builtin_amdgcn_s_waitcnt(vmcnt_encoding(kLoads));
+    else __builtin_amdgcn_s_waitcnt(vmcnt_encoding(0));
     __syncthreads();
 
-    const int nchunks = (g.clocks + kChunk - 1) / kChunk;
     for (int c = 0; c < nchunks; ++c) {
-        const int buf = c & 1;
+        const int buf = c % 3;
         const int c0 = c * kChunk;
-        if (c + 1 < nchunks) stage_load(c0 + kChunk, staged);
+        const bool ahead = c + 2 < nchunks;
+        if (ahead) stage(c0 + 2 * kChunk, (c + 2) % 3);
         Word wl_n, wr_n[DPL];
         {
             int x, row, xm, slot;
@@ -366,8 +395,9 @@ __device__ __forceinline__ void run_lines(const AggregateArgs &a, const BlockGeo
             const uint32_t qp_edge = LO::from_next(Q[0], last);
             uint32_t L[DPL];
             uint32_t m = 0xFFFFFFFFu;
-            // the block's leftmost column decides whether any lane sees x - d < 0
-            const bool border = padded || (KIND == 0 ? x : xm) < kDpad - 1;
+            // the block's leftmost column decides whether any lane sees x - d < 0;
+            // the first chunk of skewed lines has lines that have not started
+            const bool border = padded || (HORIZ ? x : xm) < kDpad - 1 || (skewed && c == 0);
             if (!border) {
 #pragma unroll
                 for (int j = 0; j < DPL; ++j) {
@@ -382,7 +412,8 @@ __device__ __forceinline__ void run_lines(const AggregateArgs &a, const BlockGeo
                 for (int j = 0; j < DPL; ++j) {
                     const int d = d0 + j;
                     const uint32_t cst = CW::hamming(wl, wr[DPL - 1 - j]);
-                    const uint32_t C = d < D ? (x - d >= 0 ? cst : bits) : kPadCost;
+                    uint32_t C = d < D ? (x - d >= 0 ? cst : bits) : kPadCost;
+                    C = s < 0 ? 0u : C;
                     const uint32_t qm = j > 0 ? Q[j - 1] : qm_edge;
                     const uint32_t qp = j < DPL - 1 ? Q[j + 1] : qp_edge;
                     const uint32_t tt = min(min(Q[j], min(qm, qp) + p1), p2);
@@ -391,30 +422,32 @@ __device__ __forceinline__ void run_lines(const AggregateArgs &a, const BlockGeo
                 }
             }
             m = LO::line_min(m);
-            if (KIND == 2 && c == 0) {
-                // lines start one clock apart; a line that has not started keeps Q = 0
 #pragma unroll
-                for (int j = 0; j < DPL; ++j) Q[j] = s >= 0 ? L[j] - m : 0u;
-            } else {
-#pragma unroll
-                for (int j = 0; j < DPL; ++j) Q[j] = L[j] - m;
-            }
+            for (int j = 0; j < DPL; ++j) Q[j] = L[j] - m;
             const size_t o = active ? ((size_t)row * W + x) * kDpad + d0 : trash;
             store_bytes<DPL>(out + o, L);
         }
-        if (c + 1 < nchunks) stage_store(buf ^ 1, staged);
-        __syncthreads();
+        // the next chunk's tile must have landed: only this chunk's look-ahead
+        // loads and its kChunk stores may still be in flight.  The tile is written
+        // by the loads themselves, so a bare s_barrier (no release fence, which
+        // would also wait for every global store) orders the waves; the empty asm
+        // statements keep the compiler from moving LDS reads across it.
+        if (ahead) __builtin_amdgcn_s_waitcnt(vmcnt_encoding(kLoads + store_ops<DPL>() * kChunk));
+        else __builtin_amdgcn_s_waitcnt(vmcnt_encoding(0));
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
     }
 }
 
 template <int DPL, bool WIDE>
 __global__ __launch_bounds__(kBlock) void aggregate_kernel(AggregateArgs a)
 {
-    using Word = typename CensusWord<WIDE>::T;
     constexpr int kDpad = kLanesPerLine * DPL;
     constexpr int kHL = horizontal_lanes(kDpad);
-    constexpr int kTile = kChunk * (kDpad + 2 * kChunk - 1);
-    __shared__ Word tile[2][kTile];
+    constexpr int kTileDw = kChunk * (kDpad + 2 * kChunk - 1) * (WIDE ? 2 : 1);
+    constexpr int kTile = (kTileDw + kBlock - 1) / kBlock * kBlock;
+    __shared__ uint32_t tile[3][kTile];
     int dir = 0;
 #pragma unroll
     for (int k = 1; k < 8; ++k)
@@ -426,11 +459,9 @@ __global__ __launch_bounds__(kBlock) void aggregate_kernel(AggregateArgs a)
         // horizontal lines are the longest dependency chains of the pass: more
         // lanes per line to shorten each step, and issue priority
         __builtin_amdgcn_s_setprio(2);
-        run_lines<kDpad / kHL, kHL, WIDE, 0, kTile>(a, g, out, tile);
-    } else if (g.kind == 1) {
-        run_lines<DPL, kLanesPerLine, WIDE, 1, kTile>(a, g, out, tile);
+        run_lines<kDpad / kHL, kHL, WIDE, true, kTile>(a, g, out, tile);
     } else {
-        run_lines<DPL, kLanesPerLine, WIDE, 2, kTile>(a, g, out, tile);
+        run_lines<DPL, kLanesPerLine, WIDE, false, kTile>(a, g, out, tile);
     }
 }
 

@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include "internal.h"
+#include "net_internal.h"
 
 namespace ss {
 
@@ -74,24 +75,7 @@ static Layout layout(const simsense_params *p)
 
 using namespace ss;
 
-struct simsense_handle {
-    simsense_params p;
-    int bits, Dpad, ndirs;
-    bool wide;
-    void *block;
-    void *census_l, *census_r;
-    uint8_t *paths[8];
-    uint8_t *disp_int, *disp_right, *flags_pre;
-    uint16_t *cost_best, *cost_second;
-    float *disp_sub, *masked;
-    hipStream_t last_stream;
-    // profiling: kProfSlots call slots of 2 events per pass
-    bool profiling;
-    int prof_used;
-    int prof_calls;
-    double prof_ms[SIMSENSE_NUM_PASSES];
-    hipEvent_t *prof_events;
-};
+
 
 namespace {
 constexpr int kProfSlots = 256;
@@ -126,6 +110,85 @@ void prof_free(simsense_handle *h)
     h->prof_events = nullptr;
 }
 }  // namespace
+
+namespace ss {
+
+int profile_begin_call(simsense_handle *h)
+{
+    if (h->profiling && h->prof_used == kProfSlots) return prof_harvest(h);
+    return SIMSENSE_OK;
+}
+
+void profile_end_call(simsense_handle *h)
+{
+    if (h->profiling) ++h->prof_used;
+}
+
+void profile_mark(simsense_handle *h, int pass, bool end, hipStream_t s)
+{
+    if (h->profiling) (void)hipEventRecord(*prof_slot(h, pass, end), s);
+}
+
+#define SS_TRY(expr) \
+    do { if ((expr) != hipSuccess) { (void)hipGetLastError(); return SIMSENSE_ERR_DEVICE; } } while (0)
+
+int enqueue_match(simsense_handle *h, const uint8_t *left, const uint8_t *right, int pitch, hipStream_t s)
+{
+    const simsense_params &p = h->p;
+    const int W = p.width, H = p.height, D = p.max_disp;
+    h->last_stream = s;
+    profile_mark(h, SIMSENSE_PASS_CENSUS, false, s);
+    SS_TRY(launch_census(left, pitch, W, H, p.census_w, p.census_h, p.census_mode, h->census_l, h->wide, s));
+    SS_TRY(launch_census(right, pitch, W, H, p.census_w, p.census_h, p.census_mode, h->census_r, h->wide, s));
+    profile_mark(h, SIMSENSE_PASS_CENSUS, true, s);
+
+    AggregateArgs ag{};
+    ag.census_l = h->census_l;
+    ag.census_r = h->census_r;
+    ag.W = W; ag.H = H; ag.D = D; ag.Dpad = h->Dpad; ag.bits = h->bits; ag.p1 = p.p1; ag.p2 = p.p2;
+    ag.ndirs = h->ndirs;
+    ag.block_begin[0] = 0;
+    for (int r = 0; r < h->ndirs; ++r) {
+        ag.dx[r] = kPathDx[r];
+        ag.dy[r] = kPathDy[r];
+        ag.out[r] = h->paths[r];
+        ag.block_begin[r + 1] = ag.block_begin[r] + aggregate_blocks(kPathDx[r], kPathDy[r], W, H, h->Dpad);
+    }
+    profile_mark(h, SIMSENSE_PASS_AGGREGATE, false, s);
+    SS_TRY(launch_aggregate(ag, h->wide, s));
+    profile_mark(h, SIMSENSE_PASS_AGGREGATE, true, s);
+
+    SelectArgs sa{};
+    for (int r = 0; r < h->ndirs; ++r) sa.paths[r] = h->paths[r];
+    sa.ndirs = h->ndirs;
+    sa.W = W; sa.H = H; sa.D = D; sa.Dpad = h->Dpad;
+    sa.uniqueness_pct = p.uniqueness_pct; sa.lr_max_diff = p.lr_max_diff; sa.subpixel = p.subpixel;
+    sa.small_values = h->bits + p.p2 <= 127;
+    sa.disp_int = h->disp_int; sa.cost_best = h->cost_best; sa.cost_second = h->cost_second;
+    sa.disp_right = h->disp_right; sa.disp_sub = h->disp_sub; sa.masked = h->masked; sa.flags = h->flags_pre;
+    profile_mark(h, SIMSENSE_PASS_SELECT, false, s);
+    SS_TRY(launch_select(sa, s));
+    profile_mark(h, SIMSENSE_PASS_SELECT, true, s);
+    return SIMSENSE_OK;
+}
+
+int enqueue_post(simsense_handle *h, const float *masked, const uint8_t *flags_pre, const simsense_outputs *o,
+                 hipStream_t s)
+{
+    const simsense_params &p = h->p;
+    PostArgs pa{};
+    pa.masked = masked; pa.flags_in = flags_pre;
+    pa.W = p.width; pa.H = p.height; pa.median = p.median;
+    pa.fb = p.focal_px * p.baseline_m;
+    pa.disp = o->disp; pa.depth = o->depth; pa.flags = o->flags;
+    profile_mark(h, SIMSENSE_PASS_POST, false, s);
+    if (pa.disp || pa.depth || pa.flags) SS_TRY(launch_post(pa, s));
+    profile_mark(h, SIMSENSE_PASS_POST, true, s);
+    return SIMSENSE_OK;
+}
+#undef SS_TRY
+
+}  // namespace ss
 
 extern "C" {
 
@@ -205,62 +268,17 @@ int simsense_compute_ex(simsense_handle *h, const uint8_t *left, const uint8_t *
     const simsense_params &p = h->p;
     if (pitch < p.width) return SIMSENSE_ERR_INVALID_ARGUMENT;
     hipStream_t s = (hipStream_t)stream;
-    h->last_stream = s;
     const int W = p.width, H = p.height, D = p.max_disp;
     const size_t npx = (size_t)W * H;
+    int rc = profile_begin_call(h);
+    if (rc != SIMSENSE_OK) return rc;
+    rc = enqueue_match(h, left, right, pitch, s);
+    if (rc != SIMSENSE_OK) return rc;
+    rc = enqueue_post(h, h->masked, h->flags_pre, o, s);
+    if (rc != SIMSENSE_OK) return rc;
+    profile_end_call(h);
 #define SS_TRY(expr) \
     do { if ((expr) != hipSuccess) { (void)hipGetLastError(); return SIMSENSE_ERR_DEVICE; } } while (0)
-    const bool prof = h->profiling;
-    if (prof && h->prof_used == kProfSlots) {
-        int rc = prof_harvest(h);
-        if (rc != SIMSENSE_OK) return rc;
-    }
-#define SS_MARK(pass, end) \
-    do { if (prof) SS_TRY(hipEventRecord(*prof_slot(h, pass, end), s)); } while (0)
-
-    SS_MARK(SIMSENSE_PASS_CENSUS, false);
-    SS_TRY(launch_census(left, pitch, W, H, p.census_w, p.census_h, p.census_mode, h->census_l, h->wide, s));
-    SS_TRY(launch_census(right, pitch, W, H, p.census_w, p.census_h, p.census_mode, h->census_r, h->wide, s));
-    SS_MARK(SIMSENSE_PASS_CENSUS, true);
-
-    AggregateArgs ag{};
-    ag.census_l = h->census_l;
-    ag.census_r = h->census_r;
-    ag.W = W; ag.H = H; ag.D = D; ag.Dpad = h->Dpad; ag.bits = h->bits; ag.p1 = p.p1; ag.p2 = p.p2;
-    ag.ndirs = h->ndirs;
-    ag.block_begin[0] = 0;
-    for (int r = 0; r < h->ndirs; ++r) {
-        ag.dx[r] = kPathDx[r];
-        ag.dy[r] = kPathDy[r];
-        ag.out[r] = h->paths[r];
-        ag.block_begin[r + 1] = ag.block_begin[r] + aggregate_blocks(kPathDx[r], kPathDy[r], W, H, h->Dpad);
-    }
-    SS_MARK(SIMSENSE_PASS_AGGREGATE, false);
-    SS_TRY(launch_aggregate(ag, h->wide, s));
-    SS_MARK(SIMSENSE_PASS_AGGREGATE, true);
-
-    SelectArgs sa{};
-    for (int r = 0; r < h->ndirs; ++r) sa.paths[r] = h->paths[r];
-    sa.ndirs = h->ndirs;
-    sa.W = W; sa.H = H; sa.D = D; sa.Dpad = h->Dpad;
-    sa.uniqueness_pct = p.uniqueness_pct; sa.lr_max_diff = p.lr_max_diff; sa.subpixel = p.subpixel;
-    sa.small_values = h->bits + p.p2 <= 127;
-    sa.disp_int = h->disp_int; sa.cost_best = h->cost_best; sa.cost_second = h->cost_second;
-    sa.disp_right = h->disp_right; sa.disp_sub = h->disp_sub; sa.masked = h->masked; sa.flags = h->flags_pre;
-    SS_MARK(SIMSENSE_PASS_SELECT, false);
-    SS_TRY(launch_select(sa, s));
-    SS_MARK(SIMSENSE_PASS_SELECT, true);
-
-    PostArgs pa{};
-    pa.masked = h->masked; pa.flags_in = h->flags_pre;
-    pa.W = W; pa.H = H; pa.median = p.median;
-    pa.fb = p.focal_px * p.baseline_m;
-    pa.disp = o->disp; pa.depth = o->depth; pa.flags = o->flags;
-    SS_MARK(SIMSENSE_PASS_POST, false);
-    if (pa.disp || pa.depth || pa.flags) SS_TRY(launch_post(pa, s));
-    SS_MARK(SIMSENSE_PASS_POST, true);
-    if (prof) ++h->prof_used;
-
     if (o->disp_int) SS_TRY(hipMemcpyAsync(o->disp_int, h->disp_int, npx, hipMemcpyDeviceToDevice, s));
     if (o->cost_best) SS_TRY(hipMemcpyAsync(o->cost_best, h->cost_best, npx * 2, hipMemcpyDeviceToDevice, s));
     if (o->cost_second)
@@ -276,7 +294,14 @@ int simsense_compute_ex(simsense_handle *h, const uint8_t *left, const uint8_t *
         for (int r = 0; r < h->ndirs; ++r) ps.p[r] = h->paths[r];
         SS_TRY(launch_volume_sum(ps, h->ndirs, W, H, D, h->Dpad, o->volume, s));
     }
-#undef SS_MARK
+    if (o->features) {
+        net::FeatureArgs fa{};
+        fa.ir = left; fa.pitch = pitch; fa.W = W;
+        fa.s1 = h->cost_best; fa.s2 = h->cost_second; fa.dint = h->disp_int;
+        fa.max_disp = D; fa.smax = (float)(h->ndirs * (h->bits + p.p2));
+        fa.features = o->features; fa.P = (int64_t)npx;
+        SS_TRY(net::launch_features(fa, s));
+    }
 #undef SS_TRY
     return SIMSENSE_OK;
 }

@@ -77,4 +77,35 @@ struct PathSet {
 hipError_t launch_volume_sum(const PathSet &paths, int ndirs, int W, int H, int D, int Dpad,
                              uint16_t *out, hipStream_t s);
 
+// ---------------------------------------------------------------- handle
+// Work common to the compute entry points; each returns a simsense_status.
+//  enqueue_match: census, aggregation and selection into the handle's scratch
+//                 (d*, S1, S2, dR, sub-pixel, masked disparity, flags bits 0..2);
+//  enqueue_post:  median + depth of a masked map into the caller's outputs.
+int enqueue_match(simsense_handle *h, const uint8_t *left, const uint8_t *right, int pitch, hipStream_t s);
+int enqueue_post(simsense_handle *h, const float *masked, const uint8_t *flags_pre, const simsense_outputs *o,
+                 hipStream_t s);
+int profile_begin_call(simsense_handle *h);
+void profile_end_call(simsense_handle *h);
+void profile_mark(simsense_handle *h, int pass, bool end, hipStream_t s);
+
 }  // namespace ss
+
+struct simsense_handle {  // opaque to callers
+    simsense_params p;
+    int bits, Dpad, ndirs;
+    bool wide;
+    void *block;
+    void *census_l, *census_r;
+    uint8_t *paths[8];
+    uint8_t *disp_int, *disp_right, *flags_pre;
+    uint16_t *cost_best, *cost_second;
+    float *disp_sub, *masked;
+    hipStream_t last_stream;
+    // profiling: call slots of 2 events per pass
+    bool profiling;
+    int prof_used;
+    int prof_calls;
+    double prof_ms[SIMSENSE_NUM_PASSES];
+    hipEvent_t *prof_events;
+};

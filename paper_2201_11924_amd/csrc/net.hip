@@ -1,0 +1,503 @@
+// Learned surrogate: a 4-layer 3x3 convolutional net (4 -> 32 -> 32 -> 32 -> 2,
+// ReLU after the first three, zero padding) on features of a 2-path SGM result,
+// predicting a disparity residual and a validity logit.  BF16 weights and
+// activations, FP32 accumulation on the gfx950 matrix cores, hand-written
+// forward, backward (data and weight) and Adam kernels.
+//
+// Layouts.  Activations are NHWC bf16 with the channel count padded to 8 (the
+// 4 feature channels, the 2 output-gradient channels) or 32.  A convolution is
+// an implicit GEMM out[co][p] = sum_k Wk[co][k] * X[k][p] with k = tap * CINP + ci
+// (tap = 3*ky + kx), computed by v_mfma_f32_16x16x32_bf16 with the weights as the
+// A operand (16 output channels x 32 k) and the activations as the B operand
+// (32 k x 16 pixels): a lane then owns 4 consecutive output channels of one
+// pixel, i.e. 8 contiguous bytes of the NHWC output.  The backward-data pass is
+// the same kernel with the taps mirrored and the channel roles swapped.
+#include <math.h>
+#include <string.h>
+
+#include "internal.h"
+#include "net_internal.h"
+
+namespace ss {
+namespace net {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    // round to nearest, ties to even (inputs here are finite)
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ bf16x8 as_bf16x8(uint4 v)
+{
+    bf16x8 r;
+    __builtin_memcpy(&r, &v, sizeof(r));
+    return r;
+}
+
+// ------------------------------------------------------------------ forward / backward-data
+
+constexpr int kConvTilesPerWave = 4;  // 16-pixel tiles per wave (weights stay in registers)
+
+template <int CINP, int COUTP, int EPI>
+__global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a)
+{
+    constexpr int KPAD = kpad(CINP);
+    constexpr int NK = KPAD / 32;
+    constexpr int MB = COUTP / 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int quad = lane >> 4, col = lane & 15;
+    const uint16_t *__restrict__ wk = a.weights;
+
+    // A fragments (weights): lane holds co = 16*mb + col, k = 32*c + 8*quad .. +7
+    bf16x8 wa[MB][NK];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int c = 0; c < NK; ++c)
+            wa[mb][c] = as_bf16x8(*(const uint4 *)(wk + (size_t)(16 * mb + col) * KPAD + 32 * c + 8 * quad));
+    float bias[MB][4];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bias[mb][i] = a.bias ? a.bias[16 * mb + 4 * quad + i] : 0.0f;
+
+    const int64_t P = (int64_t)a.batch * a.H * a.W;
+    const int64_t tile0 = ((int64_t)blockIdx.x * 4 + wave) * kConvTilesPerWave;
+    for (int tt = 0; tt < kConvTilesPerWave; ++tt) {
+        const int64_t p = (tile0 + tt) * 16 + col;  // this lane's pixel (B operand column)
+        if ((tile0 + tt) * 16 >= P) break;
+        int b = 0, y = 0, x = 0;
+        if (p < P) {
+            b = (int)(p / ((int64_t)a.H * a.W));
+            const int r = (int)(p - (int64_t)b * a.H * a.W);
+            y = r / a.W;
+            x = r - y * a.W;
+        }
+        floatx4 acc[MB];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) acc[mb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < NK; ++c) {
+            // B fragment: k = 32*c + 8*quad .. +7 of pixel p
+            const int k8 = 32 * c + 8 * quad;
+            const int tap = k8 / CINP, ch = k8 - tap * CINP;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (tap < 9 && p < P) {
+                const int sy = y + tap / 3 - 1, sx = x + tap % 3 - 1;
+                if (sy >= 0 && sy < a.H && sx >= 0 && sx < a.W)
+                    v = *(const uint4 *)(a.in + (((int64_t)b * a.H + sy) * a.W + sx) * CINP + ch);
+            }
+            const bf16x8 bv = as_bf16x8(v);
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+                acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[mb][c], bv, acc[mb], 0, 0, 0);
+        }
+        if (p >= P) continue;
+        // D layout: lane holds rows (output channels) 4*quad .. +3 of column (pixel) col
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            const int co = 16 * mb + 4 * quad;
+            if (EPI == EPI_LINEAR) {
+                if (co == 0) {
+                    float *o = (float *)a.out + p * 2;
+                    o[0] = acc[mb][0] + bias[mb][0];
+                    o[1] = acc[mb][1] + bias[mb][1];
+                }
+            } else {
+                uint16_t h[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    float v = acc[mb][i];
+                    if (EPI == EPI_RELU) {
+                        v = fmaxf(v + bias[mb][i], 0.0f);
+                    } else {
+                        const uint16_t mk = a.mask[p * COUTP + co + i];
+                        v = (mk & 0x7FFF) != 0 && !(mk & 0x8000) ? v : 0.0f;  // mask > 0
+                    }
+                    h[i] = f2bf(v);
+                }
+                uint2 w;
+                w.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
+                w.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
+                *(uint2 *)((uint16_t *)a.out + p * COUTP + co) = w;
+            }
+        }
+    }
+}
+
+hipError_t launch_conv(const ConvArgs &a, int cinp, int coutp, int epi, hipStream_t s)
+{
+    const int64_t P = (int64_t)a.batch * a.H * a.W;
+    const int64_t tiles = (P + 15) / 16;
+    const int64_t blocks = (tiles + 4 * kConvTilesPerWave - 1) / (4 * kConvTilesPerWave);
+    dim3 grid((unsigned)blocks), block(256);
+#define SS_CONV(CI, CO, E)                                                                \
+    if (cinp == CI && coutp == CO && epi == E) {                                          \
+        hipLaunchKernelGGL((conv3x3_kernel<CI, CO, E>), grid, block, 0, s, a);            \
+        return hipGetLastError();                                                         \
+    }
+    SS_CONV(8, 32, EPI_RELU)      // layer 1
+    SS_CONV(32, 32, EPI_RELU)     // layers 2, 3
+    SS_CONV(32, 16, EPI_LINEAR)   // layer 4 (2 real outputs)
+    SS_CONV(32, 32, EPI_MASK)     // backward-data of layers 2, 3
+    SS_CONV(16, 32, EPI_MASK)     // backward-data of layer 4 (2 real gradient channels)
+#undef SS_CONV
+    return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------ weight gradient
+// dW[co][k] = sum_p dY[p][co] * X[p + tap(k)][ci(k)]: a GEMM with M = COUT, N = 9*CINP
+// and K = pixels.  A block takes a range of image rows; per 32-pixel segment of a
+// row it stages dY transposed ([co][32 px]) and the three input rows transposed
+// ([kx][ci][row][32 px], one copy per horizontal tap offset so that every fragment
+// is one aligned 16-byte LDS read), then each wave accumulates its 16x16 output
+// tiles.  Per-block partial sums are written out and reduced in a fixed order.
+template <int CINP, int COUTP>
+__global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a)
+{
+    constexpr int NB = (9 * CINP + 15) / 16;    // N blocks of 16 (k = tap*CINP + ci)
+    constexpr int MB = COUTP / 16;
+    constexpr int TILES = MB * NB;
+    constexpr int TPW = (TILES + 3) / 4;        // tiles per wave
+    __shared__ __align__(16) uint16_t sdy[32][32];             // [co][px]
+    __shared__ __align__(16) uint16_t sx[3][CINP][3][32];      // [kx][ci][row][px]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int quad = lane >> 4, col = lane & 15;
+    floatx4 acc[TPW];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    const int rows = a.batch * a.H;
+    const int r0 = (int)(((int64_t)rows * blockIdx.x) / gridDim.x);
+    const int r1 = (int)(((int64_t)rows * (blockIdx.x + 1)) / gridDim.x);
+    const int segs = (a.W + 31) / 32;
+    for (int r = r0; r < r1; ++r) {
+        const int b = r / a.H, y = r - b * a.H;
+        for (int sg = 0; sg < segs; ++sg) {
+            const int x0 = sg * 32;
+            __syncthreads();
+            // stage dY (COUTP channels, zero past the row end and past COUTP)
+            for (int i = threadIdx.x; i < 32 * 32; i += 256) {
+                const int px = i & 31, co = i >> 5;
+                uint16_t v = 0;
+                if (co < COUTP && x0 + px < a.W) v = a.dy[(((int64_t)b * a.H + y) * a.W + x0 + px) * COUTP + co];
+                sdy[co][px] = v;
+            }
+            // stage X rows y-1..y+1, columns x0-1 .. x0+32, three shifted copies
+            for (int i = threadIdx.x; i < 3 * CINP * 3 * 32; i += 256) {
+                const int px = i & 31;
+                const int rr = (i >> 5) % 3;
+                const int ci = ((i >> 5) / 3) % CINP;
+                const int kx = (i >> 5) / (3 * CINP);
+                const int sy = y + rr - 1, sxx = x0 + px + kx - 1;
+                uint16_t v = 0;
+                if (sy >= 0 && sy < a.H && sxx >= 0 && sxx < a.W && x0 + px < a.W)
+                    v = a.x[(((int64_t)b * a.H + sy) * a.W + sxx) * CINP + ci];
+                sx[kx][ci][rr][px] = v;
+            }
+            __syncthreads();
+            // K-step of 32 pixels: this lane's pixels are 8*quad .. +7
+#pragma unroll
+            for (int t = 0; t < TPW; ++t) {
+                const int tile = wave + 4 * t;
+                if (tile >= TILES) break;
+                const int mb = tile % MB, nb = tile / MB;
+                const bf16x8 av = as_bf16x8(*(const uint4 *)&sdy[16 * mb + col][8 * quad]);
+                const int k = 16 * nb + col;
+                const int tap = k / CINP, ci = k - tap * CINP;
+                uint4 raw = make_uint4(0, 0, 0, 0);
+                if (tap < 9) raw = *(const uint4 *)&sx[tap % 3][ci][tap / 3][8 * quad];
+                const bf16x8 bv = as_bf16x8(raw);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[t], 0, 0, 0);
+            }
+        }
+    }
+    // partial[block][co][k]
+    float *part = a.partial + (size_t)blockIdx.x * COUTP * 9 * CINP;
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+        const int tile = wave + 4 * t;
+        if (tile >= TILES) break;
+        const int mb = tile % MB, nb = tile / MB;
+        if (16 * nb + col >= 9 * CINP) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) part[(size_t)(16 * mb + 4 * quad + i) * 9 * CINP + 16 * nb + col] = acc[t][i];
+    }
+}
+
+// bias gradient partials: partial[block][co] = sum over the block's pixels of dY[p][co]
+template <int COUTP>
+__global__ __launch_bounds__(256) void bgrad_kernel(WgradArgs a)
+{
+    __shared__ float red[256];
+    const int64_t P = (int64_t)a.batch * a.H * a.W;
+    const int co = threadIdx.x % COUTP, lanes = 256 / COUTP, sub = threadIdx.x / COUTP;
+    const int64_t p0 = (P * blockIdx.x) / gridDim.x, p1 = (P * (blockIdx.x + 1)) / gridDim.x;
+    float s = 0.0f;
+    for (int64_t p = p0 + sub; p < p1; p += lanes) s += bf2f(a.dy[p * COUTP + co]);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x < COUTP) {
+        float t = 0.0f;
+        for (int i = 0; i < lanes; ++i) t += red[i * COUTP + threadIdx.x];
+        a.bpartial[(size_t)blockIdx.x * COUTP + threadIdx.x] = t;
+    }
+}
+
+// grad[off + ((tap*CIN + ci)*COUT + co)] = sum over blocks of partial[block][co][tap*CINP + ci];
+// grad[boff + co] = sum over blocks of bpartial[block][co]   (fixed order: deterministic)
+__global__ __launch_bounds__(256) void wgrad_reduce_kernel(WgradReduceArgs a)
+{
+    const int nw = 9 * a.cin * a.cout;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < nw) {
+        const int co = i % a.cout, ci = (i / a.cout) % a.cin, tap = i / (a.cout * a.cin);
+        const size_t stride = (size_t)a.coutp * 9 * a.cinp;
+        const size_t idx = (size_t)co * 9 * a.cinp + tap * a.cinp + ci;
+        float s = 0.0f;
+        for (int blk = 0; blk < a.nblocks; ++blk) s += a.partial[blk * stride + idx];
+        a.grad[a.woff + i] = s;
+    } else if (i < nw + a.cout) {
+        const int co = i - nw;
+        float s = 0.0f;
+        for (int blk = 0; blk < a.nbblocks; ++blk) s += a.bpartial[(size_t)blk * a.coutp + co];
+        a.grad[a.boff + co] = s;
+    }
+}
+
+hipError_t launch_wgrad(const WgradArgs &a, int cinp, int coutp, int nblocks, int nbblocks, hipStream_t s)
+{
+    if (cinp == 8 && coutp == 32) hipLaunchKernelGGL((wgrad_kernel<8, 32>), dim3(nblocks), dim3(256), 0, s, a);
+    else if (cinp == 32 && coutp == 32) hipLaunchKernelGGL((wgrad_kernel<32, 32>), dim3(nblocks), dim3(256), 0, s, a);
+    else if (cinp == 32 && coutp == 16) hipLaunchKernelGGL((wgrad_kernel<32, 16>), dim3(nblocks), dim3(256), 0, s, a);
+    else return hipErrorInvalidValue;
+    if (coutp == 32) hipLaunchKernelGGL((bgrad_kernel<32>), dim3(nbblocks), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((bgrad_kernel<16>), dim3(nbblocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_wgrad_reduce(const WgradReduceArgs &a, hipStream_t s)
+{
+    const int n = 9 * a.cin * a.cout + a.cout;
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((n + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ loss
+// Per pixel: L1 term |r - t| on 8-path-valid pixels, BCE-with-logits term on all
+// pixels; the output gradient goes to dY (bf16, 16 channels: dr, dz, 0...).
+// Per-block partial sums: [l1, valid count, bce]; the final sums are taken in a
+// fixed order by loss_reduce_kernel, which also stores 1/count and 1/N used by
+// the gradient pass.
+__global__ __launch_bounds__(256) void count_kernel(LossArgs a)
+{
+    __shared__ float red[256];
+    const int64_t P = a.P;
+    const int64_t p0 = (P * blockIdx.x) / gridDim.x, p1 = (P * (blockIdx.x + 1)) / gridDim.x;
+    float c = 0.0f;
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += 256) c += a.t_valid[p] ? 1.0f : 0.0f;
+    red[threadIdx.x] = c;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a.partial[blockIdx.x * 3 + 1] = red[0];
+}
+
+__global__ __launch_bounds__(256) void count_reduce_kernel(LossArgs a, int nblocks)
+{
+    if (threadIdx.x != 0) return;
+    float c = 0.0f;
+    for (int i = 0; i < nblocks; ++i) c += a.partial[i * 3 + 1];
+    a.scal[0] = c;
+    a.scal[1] = 1.0f / fmaxf(c, 1.0f);
+    a.scal[2] = 1.0f / (float)a.P;
+}
+
+__global__ __launch_bounds__(256) void loss_kernel(LossArgs a)
+{
+    __shared__ float r1[256], r3[256];
+    const int64_t P = a.P;
+    const float inv_nv = a.scal[1], inv_n = a.scal[2];
+    const int64_t p0 = (P * blockIdx.x) / gridDim.x, p1 = (P * (blockIdx.x + 1)) / gridDim.x;
+    float l1 = 0.0f, bce = 0.0f;
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += 256) {
+        const float r = a.out[p * 2], z = a.out[p * 2 + 1];
+        const float t = a.t_res[p];
+        const float v = a.t_valid[p] ? 1.0f : 0.0f;
+        const float e = r - t;
+        l1 += fabsf(e) * v;
+        bce += fmaxf(z, 0.0f) - z * v + log1pf(expf(-fabsf(z)));
+        const float dr = (e > 0.0f ? 1.0f : (e < 0.0f ? -1.0f : 0.0f)) * v * inv_nv;
+        const float dz = (1.0f / (1.0f + expf(-z)) - v) * inv_n;
+        uint4 w = make_uint4((uint32_t)f2bf(dr) | ((uint32_t)f2bf(dz) << 16), 0, 0, 0);
+        uint4 *dst = (uint4 *)(a.dy + p * 16);
+        dst[0] = w;
+        dst[1] = make_uint4(0, 0, 0, 0);
+    }
+    r1[threadIdx.x] = l1;
+    r3[threadIdx.x] = bce;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            r1[threadIdx.x] += r1[threadIdx.x + st];
+            r3[threadIdx.x] += r3[threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        a.partial[blockIdx.x * 3 + 0] = r1[0];
+        a.partial[blockIdx.x * 3 + 2] = r3[0];
+    }
+}
+
+__global__ __launch_bounds__(64) void loss_reduce_kernel(LossArgs a, int nblocks)
+{
+    if (threadIdx.x != 0) return;
+    float l1 = 0.0f, bce = 0.0f;
+    for (int i = 0; i < nblocks; ++i) {
+        l1 += a.partial[i * 3 + 0];
+        bce += a.partial[i * 3 + 2];
+    }
+    l1 *= a.scal[1];
+    bce *= a.scal[2];
+    a.loss[0] = l1 + bce;
+    a.loss[1] = l1;
+    a.loss[2] = bce;
+}
+
+hipError_t launch_loss(const LossArgs &a, int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(count_kernel, dim3(nblocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(count_reduce_kernel, dim3(1), dim3(64), 0, s, a, nblocks);
+    hipLaunchKernelGGL(loss_kernel, dim3(nblocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(64), 0, s, a, nblocks);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ Adam + weight layouts
+__global__ __launch_bounds__(256) void adam_kernel(AdamArgs a)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= a.n) return;
+    const float g = a.grad[i];
+    const float m = a.b1 * a.m[i] + (1.0f - a.b1) * g;
+    const float v = a.b2 * a.v[i] + (1.0f - a.b2) * g * g;
+    a.m[i] = m;
+    a.v[i] = v;
+    const float mh = m / a.c1, vh = v / a.c2;
+    a.p[i] -= a.lr * mh / (sqrtf(vh) + a.eps);
+}
+
+// bf16 GEMM layouts of every layer from the fp32 master parameters:
+//   forward        wf[co][tap*CINP + ci]        = W[tap][ci][co]
+//   backward-data  wb[ci][tap'*COUTP' + co]     = W[8 - tap'][ci][co]   (mirrored taps)
+__global__ __launch_bounds__(256) void relayout_kernel(RelayoutArgs a)
+{
+    const int L = blockIdx.y;
+    const LayerDesc d = a.layer[L];
+    const int nf = d.coutp * kpad(d.cinp);
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const float *W = a.params + d.woff;
+    if (i < nf) {
+        const int co = i / kpad(d.cinp), k = i - co * kpad(d.cinp);
+        const int tap = k / d.cinp, ci = k - tap * d.cinp;
+        float v = 0.0f;
+        if (co < d.cout && tap < 9 && ci < d.cin) v = W[(tap * d.cin + ci) * d.cout + co];
+        d.wf[i] = f2bf(v);
+    }
+    if (d.wb) {
+        const int nb = d.cinp_b * kpad(d.coutp_b);  // rows = input channels (32), k over output channels
+        if (i < nb) {
+            const int ci = i / kpad(d.coutp_b), k = i - ci * kpad(d.coutp_b);
+            const int tap = k / d.coutp_b, co = k - tap * d.coutp_b;
+            float v = 0.0f;
+            if (ci < d.cin && tap < 9 && co < d.cout) v = W[((8 - tap) * d.cin + ci) * d.cout + co];
+            d.wb[i] = f2bf(v);
+        }
+    }
+    if (i < d.coutp) d.bias[i] = i < d.cout ? a.params[d.boff + i] : 0.0f;
+}
+
+hipError_t launch_adam(const AdamArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(adam_kernel, dim3((a.n + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_relayout(const RelayoutArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(relayout_kernel, dim3((32 * 320 + 255) / 256, 4), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ features / combine
+// features[p] = bf16 {IR/255, S1/Smax, S2/Smax, d*/D, 0, 0, 0, 0} of a 2-path result
+__global__ __launch_bounds__(256) void features_kernel(FeatureArgs a)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= a.P) return;
+    const int64_t y = p / a.W, x = p - y * a.W;
+    const float ir = (float)a.ir[y * a.pitch + x];
+    const float s1 = (float)a.s1[p];
+    const uint32_t s2r = a.s2[p];
+    const float s2 = s2r == 0xFFFFu ? a.smax : fminf((float)s2r, a.smax);
+    const float f0 = ir / 255.0f, f1 = s1 / a.smax, f2 = s2 / a.smax, f3 = (float)a.dint[p] / (float)a.max_disp;
+    uint4 w;
+    w.x = (uint32_t)f2bf(f0) | ((uint32_t)f2bf(f1) << 16);
+    w.y = (uint32_t)f2bf(f2) | ((uint32_t)f2bf(f3) << 16);
+    w.z = 0;
+    w.w = 0;
+    *(uint4 *)(a.features + p * 8) = w;
+}
+
+// masked[p] = d2_sub + r where the logit is positive and the sum is positive, else 0
+__global__ __launch_bounds__(256) void combine_kernel(CombineArgs a)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= a.P) return;
+    const float d = __fadd_rn(a.d2_sub[p], a.out[p * 2]);
+    const bool ok = a.out[p * 2 + 1] > 0.0f && d > 0.0f;
+    a.masked[p] = ok ? d : 0.0f;
+    a.flags[p] = (uint8_t)(ok ? (SIMSENSE_FLAG_UNIQUE | SIMSENSE_FLAG_LR | SIMSENSE_FLAG_NONZERO) : 0u);
+}
+
+hipError_t launch_features(const FeatureArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(features_kernel, dim3((unsigned)((a.P + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// t_res = d8_sub - d2_sub; t_valid = the 8-path result passed uniqueness, LR and d* > 0
+__global__ __launch_bounds__(256) void targets_kernel(const float *d8_sub, const uint8_t *flags8, const float *d2_sub,
+                                                      float *t_res, uint8_t *t_valid, int64_t n)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    t_res[p] = __fsub_rn(d8_sub[p], d2_sub[p]);
+    t_valid[p] = (flags8[p] & 7u) == 7u;
+}
+
+hipError_t launch_targets(const float *d8_sub, const uint8_t *flags8, const float *d2_sub, float *t_res,
+                          uint8_t *t_valid, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(targets_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d8_sub, flags8, d2_sub,
+                       t_res, t_valid, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(const CombineArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(combine_kernel, dim3((unsigned)((a.P + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace net
+}  // namespace ss

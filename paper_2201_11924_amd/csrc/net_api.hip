@@ -1,0 +1,381 @@
+// C ABI of the learned surrogate: the net handle (parameters, Adam state,
+// activations), its forward and training step, and the learned depth path
+// (2-path matching -> features -> net -> combine -> median/depth).
+#include <math.h>
+#include <new>
+#include <string.h>
+
+#include "internal.h"
+#include "net_internal.h"
+
+namespace ss {
+namespace net {
+
+struct LayerShape {
+    int cin, cout, cinp, coutp;
+};
+constexpr LayerShape kLayers[4] = {{4, 32, 8, 32}, {32, 32, 32, 32}, {32, 32, 32, 32}, {32, 2, 32, 16}};
+constexpr int kNumParams = 9 * 4 * 32 + 32 + 2 * (9 * 32 * 32 + 32) + 9 * 32 * 2 + 2;  // 20258
+constexpr int kLossBlocks = 256, kBiasBlocks = 256, kMaxWgradBlocks = 512;
+
+int woff(int l)
+{
+    int o = 0;
+    for (int i = 0; i < l; ++i) o += 9 * kLayers[i].cin * kLayers[i].cout + kLayers[i].cout;
+    return o;
+}
+int boff(int l) { return woff(l) + 9 * kLayers[l].cin * kLayers[l].cout; }
+
+}  // namespace net
+}  // namespace ss
+
+using namespace ss;
+using namespace ss::net;
+
+struct simsense_net {
+    int64_t max_pixels;
+    int64_t step;
+    void *block;
+    float *params, *m, *v, *grad;
+    uint16_t *wf[4], *wb[4];
+    float *bias[4];
+    uint16_t *feat;        // [P][8] features of the learned depth path
+    uint16_t *act[3];      // [P][32] outputs of layers 1..3
+    float *out;            // [P][2]
+    uint16_t *dy4;         // [P][16]
+    uint16_t *g[2];        // [P][32] backward ping-pong
+    float *wpart, *bpart;  // weight / bias gradient partials
+    float *lpart, *scal, *loss;
+    float *t_res;          // targets of the learned depth path's own use (training helpers)
+    uint8_t *t_valid;
+    hipStream_t last_stream;
+};
+
+namespace {
+
+size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// host-side deterministic init: He-uniform weights from a splitmix64 stream, zero biases
+uint64_t splitmix64(uint64_t &s)
+{
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+void init_params(float *host, uint64_t seed)
+{
+    uint64_t s = seed;
+    for (int l = 0; l < 4; ++l) {
+        const int nw = 9 * kLayers[l].cin * kLayers[l].cout;
+        const double bound = sqrt(6.0 / (9.0 * kLayers[l].cin));
+        for (int i = 0; i < nw; ++i) {
+            const double u = (double)(splitmix64(s) >> 11) * (1.0 / 9007199254740992.0);
+            host[woff(l) + i] = (float)((2.0 * u - 1.0) * bound);
+        }
+        for (int i = 0; i < kLayers[l].cout; ++i) host[boff(l) + i] = 0.0f;
+    }
+}
+
+RelayoutArgs relayout_args(simsense_net *n)
+{
+    RelayoutArgs r{};
+    r.params = n->params;
+    for (int l = 0; l < 4; ++l) {
+        LayerDesc &d = r.layer[l];
+        d.cin = kLayers[l].cin;
+        d.cout = kLayers[l].cout;
+        d.cinp = kLayers[l].cinp;
+        d.coutp = kLayers[l].coutp;
+        d.cinp_b = kLayers[l].cinp;   // rows of the backward-data GEMM: this layer's input channels
+        d.coutp_b = kLayers[l].coutp; // its k runs over this layer's (padded) output channels
+        d.woff = woff(l);
+        d.boff = boff(l);
+        d.wf = n->wf[l];
+        d.wb = l > 0 ? n->wb[l] : nullptr;
+        d.bias = n->bias[l];
+    }
+    return r;
+}
+
+#define NET_TRY(expr) \
+    do { if ((expr) != hipSuccess) { (void)hipGetLastError(); return SIMSENSE_ERR_DEVICE; } } while (0)
+
+int enqueue_forward(simsense_net *n, const uint16_t *x0, int batch, int H, int W, hipStream_t s)
+{
+    ConvArgs c{};
+    c.batch = batch; c.H = H; c.W = W;
+    const uint16_t *in = x0;
+    for (int l = 0; l < 3; ++l) {
+        c.in = in; c.weights = n->wf[l]; c.bias = n->bias[l]; c.mask = nullptr; c.out = n->act[l];
+        NET_TRY(launch_conv(c, kLayers[l].cinp, kLayers[l].coutp, EPI_RELU, s));
+        in = n->act[l];
+    }
+    c.in = in; c.weights = n->wf[3]; c.bias = n->bias[3]; c.out = n->out;
+    NET_TRY(launch_conv(c, 32, 16, EPI_LINEAR, s));
+    return SIMSENSE_OK;
+}
+
+int check_shape(simsense_net *n, int batch, int H, int W)
+{
+    if (batch < 1 || H < 1 || W < 1) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    if ((int64_t)batch * H * W > n->max_pixels) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    return SIMSENSE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t simsense_net_num_params(void) { return kNumParams; }
+
+int simsense_net_create(int64_t max_pixels, uint64_t seed, simsense_net **out)
+{
+    if (!out) return SIMSENSE_ERR_NULL_POINTER;
+    if (max_pixels < 1 || max_pixels > ((int64_t)1 << 31)) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    simsense_net *n = new (std::nothrow) simsense_net();
+    if (!n) return SIMSENSE_ERR_OUT_OF_MEMORY;
+    n->max_pixels = max_pixels;
+    const size_t P = (size_t)max_pixels;
+    const int wblocks = kMaxWgradBlocks;
+    size_t sz[32];
+    int k = 0;
+    for (int i = 0; i < 4; ++i) sz[k++] = a256(kNumParams * sizeof(float));          // params, m, v, grad
+    for (int l = 0; l < 4; ++l) sz[k++] = a256(kLayers[l].coutp * kpad(kLayers[l].cinp) * 2);  // wf
+    for (int l = 0; l < 4; ++l) sz[k++] = a256(kLayers[l].cinp * kpad(kLayers[l].coutp) * 2);  // wb
+    for (int l = 0; l < 4; ++l) sz[k++] = a256(kLayers[l].coutp * sizeof(float));              // bias
+    sz[k++] = a256(P * 16);          // feat
+    for (int l = 0; l < 3; ++l) sz[k++] = a256(P * 64);  // act
+    sz[k++] = a256(P * 8);           // out
+    sz[k++] = a256(P * 32);          // dy4
+    sz[k++] = a256(P * 64);          // g0
+    sz[k++] = a256(P * 64);          // g1
+    sz[k++] = a256((size_t)wblocks * 32 * 9 * 32 * sizeof(float));  // wpart
+    sz[k++] = a256((size_t)kBiasBlocks * 32 * sizeof(float));       // bpart
+    sz[k++] = a256((size_t)kLossBlocks * 3 * sizeof(float));        // lpart
+    sz[k++] = a256(3 * sizeof(float));                              // scal
+    sz[k++] = a256(3 * sizeof(float));                              // loss
+    sz[k++] = a256(P * 4);           // t_res
+    sz[k++] = a256(P);               // t_valid
+    size_t total = 0;
+    for (int i = 0; i < k; ++i) total += sz[i];
+    if (hipMalloc(&n->block, total) != hipSuccess) {
+        (void)hipGetLastError();
+        delete n;
+        return SIMSENSE_ERR_OUT_OF_MEMORY;
+    }
+    uint8_t *cur = (uint8_t *)n->block;
+    k = 0;
+    auto take = [&]() { void *p = cur; cur += sz[k++]; return p; };
+    n->params = (float *)take(); n->m = (float *)take(); n->v = (float *)take(); n->grad = (float *)take();
+    for (int l = 0; l < 4; ++l) n->wf[l] = (uint16_t *)take();
+    for (int l = 0; l < 4; ++l) n->wb[l] = (uint16_t *)take();
+    for (int l = 0; l < 4; ++l) n->bias[l] = (float *)take();
+    n->feat = (uint16_t *)take();
+    for (int l = 0; l < 3; ++l) n->act[l] = (uint16_t *)take();
+    n->out = (float *)take();
+    n->dy4 = (uint16_t *)take();
+    n->g[0] = (uint16_t *)take();
+    n->g[1] = (uint16_t *)take();
+    n->wpart = (float *)take();
+    n->bpart = (float *)take();
+    n->lpart = (float *)take();
+    n->scal = (float *)take();
+    n->loss = (float *)take();
+    n->t_res = (float *)take();
+    n->t_valid = (uint8_t *)take();
+    n->last_stream = nullptr;
+    n->step = 0;
+    float *host = new (std::nothrow) float[kNumParams];
+    if (!host) { (void)hipFree(n->block); delete n; return SIMSENSE_ERR_OUT_OF_MEMORY; }
+    init_params(host, seed);
+    int rc = SIMSENSE_OK;
+    if (hipMemcpy(n->params, host, kNumParams * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(n->m, 0, kNumParams * sizeof(float)) != hipSuccess ||
+        hipMemset(n->v, 0, kNumParams * sizeof(float)) != hipSuccess ||
+        hipMemset(n->grad, 0, kNumParams * sizeof(float)) != hipSuccess ||
+        launch_relayout(relayout_args(n), nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+        rc = SIMSENSE_ERR_DEVICE;
+    delete[] host;
+    if (rc != SIMSENSE_OK) {
+        (void)hipGetLastError();
+        (void)hipFree(n->block);
+        delete n;
+        return rc;
+    }
+    *out = n;
+    return SIMSENSE_OK;
+}
+
+int simsense_net_destroy(simsense_net *n)
+{
+    if (!n) return SIMSENSE_OK;
+    int rc = SIMSENSE_OK;
+    if (hipStreamSynchronize(n->last_stream) != hipSuccess) rc = SIMSENSE_ERR_DEVICE;
+    if (hipFree(n->block) != hipSuccess) rc = SIMSENSE_ERR_DEVICE;
+    delete n;
+    return rc;
+}
+
+int simsense_net_get_state(simsense_net *n, float *params, float *m, float *v, int64_t count, int64_t *step)
+{
+    if (!n) return SIMSENSE_ERR_NULL_POINTER;
+    if (count != kNumParams) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    if (hipStreamSynchronize(n->last_stream) != hipSuccess) return SIMSENSE_ERR_DEVICE;
+    const size_t b = kNumParams * sizeof(float);
+    if (params && hipMemcpy(params, n->params, b, hipMemcpyDeviceToHost) != hipSuccess) return SIMSENSE_ERR_DEVICE;
+    if (m && hipMemcpy(m, n->m, b, hipMemcpyDeviceToHost) != hipSuccess) return SIMSENSE_ERR_DEVICE;
+    if (v && hipMemcpy(v, n->v, b, hipMemcpyDeviceToHost) != hipSuccess) return SIMSENSE_ERR_DEVICE;
+    if (step) *step = n->step;
+    return SIMSENSE_OK;
+}
+
+int simsense_net_set_state(simsense_net *n, const float *params, const float *m, const float *v, int64_t count,
+                           int64_t step)
+{
+    if (!n || !params) return SIMSENSE_ERR_NULL_POINTER;
+    if (count != kNumParams || step < 0) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    if (hipStreamSynchronize(n->last_stream) != hipSuccess) return SIMSENSE_ERR_DEVICE;
+    const size_t b = kNumParams * sizeof(float);
+    if (hipMemcpy(n->params, params, b, hipMemcpyHostToDevice) != hipSuccess) return SIMSENSE_ERR_DEVICE;
+    if ((m ? hipMemcpy(n->m, m, b, hipMemcpyHostToDevice) : hipMemset(n->m, 0, b)) != hipSuccess)
+        return SIMSENSE_ERR_DEVICE;
+    if ((v ? hipMemcpy(n->v, v, b, hipMemcpyHostToDevice) : hipMemset(n->v, 0, b)) != hipSuccess)
+        return SIMSENSE_ERR_DEVICE;
+    n->step = step;
+    if (launch_relayout(relayout_args(n), nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        (void)hipGetLastError();
+        return SIMSENSE_ERR_DEVICE;
+    }
+    return SIMSENSE_OK;
+}
+
+int simsense_net_get_grads(simsense_net *n, float *grads, int64_t count)
+{
+    if (!n || !grads) return SIMSENSE_ERR_NULL_POINTER;
+    if (count != kNumParams) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    if (hipStreamSynchronize(n->last_stream) != hipSuccess) return SIMSENSE_ERR_DEVICE;
+    if (hipMemcpy(grads, n->grad, kNumParams * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+        return SIMSENSE_ERR_DEVICE;
+    return SIMSENSE_OK;
+}
+
+int simsense_net_forward(simsense_net *n, const uint16_t *features, int32_t batch, int32_t height, int32_t width,
+                         float *out, void *stream)
+{
+    if (!n || !features || !out) return SIMSENSE_ERR_NULL_POINTER;
+    int rc = check_shape(n, batch, height, width);
+    if (rc != SIMSENSE_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    n->last_stream = s;
+    rc = enqueue_forward(n, features, batch, height, width, s);
+    if (rc != SIMSENSE_OK) return rc;
+    NET_TRY(hipMemcpyAsync(out, n->out, (size_t)batch * height * width * 2 * sizeof(float),
+                           hipMemcpyDeviceToDevice, s));
+    return SIMSENSE_OK;
+}
+
+int simsense_net_train_step(simsense_net *n, const uint16_t *features, const float *target_residual,
+                            const uint8_t *target_valid, int32_t batch, int32_t height, int32_t width, float lr,
+                            float *loss, void *stream)
+{
+    if (!n || !features || !target_residual || !target_valid) return SIMSENSE_ERR_NULL_POINTER;
+    int rc = check_shape(n, batch, height, width);
+    if (rc != SIMSENSE_OK) return rc;
+    if (!(lr >= 0.0f) || !isfinite(lr)) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    hipStream_t s = (hipStream_t)stream;
+    n->last_stream = s;
+    const int64_t P = (int64_t)batch * height * width;
+    rc = enqueue_forward(n, features, batch, height, width, s);
+    if (rc != SIMSENSE_OK) return rc;
+
+    LossArgs la{};
+    la.out = n->out; la.t_res = target_residual; la.t_valid = target_valid; la.dy = n->dy4;
+    la.partial = n->lpart; la.scal = n->scal; la.loss = n->loss; la.P = P;
+    NET_TRY(launch_loss(la, kLossBlocks, s));
+
+    const int rows = batch * height;
+    const int wblocks = rows < kMaxWgradBlocks ? rows : kMaxWgradBlocks;
+    // gradient at each layer's output, layer inputs
+    const uint16_t *dy = n->dy4;
+    const uint16_t *xin[4] = {features, n->act[0], n->act[1], n->act[2]};
+    int gi = 0;
+    for (int l = 3; l >= 0; --l) {
+        WgradArgs wa{};
+        wa.x = xin[l]; wa.dy = dy; wa.partial = n->wpart; wa.bpartial = n->bpart;
+        wa.batch = batch; wa.H = height; wa.W = width;
+        NET_TRY(launch_wgrad(wa, kLayers[l].cinp, kLayers[l].coutp, wblocks, kBiasBlocks, s));
+        WgradReduceArgs ra{};
+        ra.partial = n->wpart; ra.bpartial = n->bpart; ra.grad = n->grad;
+        ra.nblocks = wblocks; ra.nbblocks = kBiasBlocks;
+        ra.cin = kLayers[l].cin; ra.cout = kLayers[l].cout; ra.cinp = kLayers[l].cinp; ra.coutp = kLayers[l].coutp;
+        ra.woff = woff(l); ra.boff = boff(l);
+        NET_TRY(launch_wgrad_reduce(ra, s));
+        if (l > 0) {
+            // gradient at the previous layer's output: backward-data conv, masked by its ReLU
+            ConvArgs c{};
+            c.in = dy; c.weights = n->wb[l]; c.bias = nullptr; c.mask = xin[l]; c.out = n->g[gi];
+            c.batch = batch; c.H = height; c.W = width;
+            NET_TRY(launch_conv(c, kLayers[l].coutp, kLayers[l].cinp, EPI_MASK, s));
+            dy = n->g[gi];
+            gi ^= 1;
+        }
+    }
+    n->step += 1;
+    AdamArgs ad{};
+    ad.p = n->params; ad.m = n->m; ad.v = n->v; ad.grad = n->grad; ad.n = kNumParams;
+    ad.lr = lr; ad.b1 = 0.9f; ad.b2 = 0.999f; ad.eps = 1e-8f;
+    ad.c1 = (float)(1.0 - pow(0.9, (double)n->step));
+    ad.c2 = (float)(1.0 - pow(0.999, (double)n->step));
+    NET_TRY(launch_adam(ad, s));
+    NET_TRY(launch_relayout(relayout_args(n), s));
+    if (loss) NET_TRY(hipMemcpyAsync(loss, n->loss, 3 * sizeof(float), hipMemcpyDeviceToDevice, s));
+    return SIMSENSE_OK;
+}
+
+int simsense_net_targets(const float *d8_sub, const uint8_t *flags8, const float *d2_sub, float *t_res,
+                         uint8_t *t_valid, int64_t count, void *stream)
+{
+    if (count < 0) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    if (count == 0) return SIMSENSE_OK;
+    if (!d8_sub || !flags8 || !d2_sub || !t_res || !t_valid) return SIMSENSE_ERR_NULL_POINTER;
+    NET_TRY(launch_targets(d8_sub, flags8, d2_sub, t_res, t_valid, count, (hipStream_t)stream));
+    return SIMSENSE_OK;
+}
+
+int simsense_learned_compute(simsense_handle *h, simsense_net *n, const uint8_t *left, const uint8_t *right,
+                             int32_t pitch, const simsense_outputs *o, void *stream)
+{
+    if (!h || !n || !left || !right || !o) return SIMSENSE_ERR_NULL_POINTER;
+    const simsense_params &p = h->p;
+    if (pitch < p.width) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    if ((int64_t)p.width * p.height > n->max_pixels) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    hipStream_t s = (hipStream_t)stream;
+    n->last_stream = s;
+    const int64_t P = (int64_t)p.width * p.height;
+    int rc = profile_begin_call(h);
+    if (rc != SIMSENSE_OK) return rc;
+    rc = enqueue_match(h, left, right, pitch, s);
+    if (rc != SIMSENSE_OK) return rc;
+    FeatureArgs fa{};
+    fa.ir = left; fa.pitch = pitch; fa.W = p.width;
+    fa.s1 = h->cost_best; fa.s2 = h->cost_second; fa.dint = h->disp_int;
+    fa.max_disp = p.max_disp; fa.smax = (float)(h->ndirs * (h->bits + p.p2));
+    fa.features = n->feat; fa.P = P;
+    NET_TRY(launch_features(fa, s));
+    rc = enqueue_forward(n, n->feat, 1, p.height, p.width, s);
+    if (rc != SIMSENSE_OK) return rc;
+    CombineArgs ca{};
+    ca.d2_sub = h->disp_sub; ca.out = n->out; ca.masked = h->masked; ca.flags = h->flags_pre; ca.P = P;
+    NET_TRY(launch_combine(ca, s));
+    rc = enqueue_post(h, h->masked, h->flags_pre, o, s);
+    if (rc != SIMSENSE_OK) return rc;
+    profile_end_call(h);
+    if (o->disp_sub) NET_TRY(hipMemcpyAsync(o->disp_sub, h->disp_sub, P * 4, hipMemcpyDeviceToDevice, s));
+    if (o->disp_int) NET_TRY(hipMemcpyAsync(o->disp_int, h->disp_int, P, hipMemcpyDeviceToDevice, s));
+    if (o->features) NET_TRY(hipMemcpyAsync(o->features, n->feat, P * 16, hipMemcpyDeviceToDevice, s));
+    return SIMSENSE_OK;
+}
+
+}  // extern "C"

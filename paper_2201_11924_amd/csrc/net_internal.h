@@ -1,0 +1,105 @@
+// Internal declarations of the learned surrogate's kernels (not installed).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ss {
+namespace net {
+
+// GEMM depth of a 3x3 convolution over CINP padded channels, rounded up to the
+// 32-deep k-step of v_mfma_f32_16x16x32_bf16.
+__host__ __device__ constexpr int kpad(int cinp) { return (9 * cinp + 31) / 32 * 32; }
+
+// conv epilogues
+// EPI_RELU:   out = bf16(max(acc + bias, 0)), COUTP channels
+// EPI_LINEAR: out = fp32 acc + bias, channels 0 and 1 only
+// EPI_MASK:   out = bf16(acc * (mask > 0)), COUTP channels (the ReLU derivative)
+enum { EPI_RELU = 0, EPI_LINEAR = 1, EPI_MASK = 2 };
+
+struct ConvArgs {
+    const uint16_t *in;       // bf16 NHWC, CINP channels
+    const uint16_t *weights;  // bf16 [COUTP][kpad(CINP)]
+    const float *bias;        // fp32 [COUTP] or null
+    const uint16_t *mask;     // bf16 NHWC, COUTP channels (backward-data only)
+    void *out;                // bf16 NHWC COUTP channels, or fp32 [P][2] for the linear layer
+    int batch, H, W;
+};
+
+struct WgradArgs {
+    const uint16_t *x;   // layer input, bf16 NHWC CINP channels
+    const uint16_t *dy;  // gradient at the layer output, bf16 NHWC COUTP channels
+    float *partial;      // [blocks][COUTP][9*CINP]
+    float *bpartial;     // [bias blocks][COUTP]
+    int batch, H, W;
+};
+
+struct WgradReduceArgs {
+    const float *partial, *bpartial;
+    float *grad;  // flat gradient, the oracle's parameter order
+    int nblocks, nbblocks;
+    int cin, cout, cinp, coutp;
+    int woff, boff;
+};
+
+struct LossArgs {
+    const float *out;        // [P][2] residual, logit
+    const float *t_res;      // [P]
+    const uint8_t *t_valid;  // [P]
+    uint16_t *dy;            // bf16 [P][16] gradient at the net output
+    float *partial;          // [blocks][3]
+    float *scal;             // [3]: valid count, 1/count, 1/P
+    float *loss;             // [3]: total, l1, bce (device)
+    int64_t P;
+};
+
+struct AdamArgs {
+    float *p, *m, *v;
+    const float *grad;
+    int n;
+    float lr, b1, b2, eps, c1, c2;  // c1 = 1 - b1^t, c2 = 1 - b2^t
+};
+
+struct LayerDesc {
+    int cin, cout, cinp, coutp;  // real and padded channel counts
+    int cinp_b, coutp_b;         // backward-data GEMM: rows (input channels), k channels (output grads)
+    int woff, boff;              // offsets in the flat parameter vector
+    uint16_t *wf, *wb;           // forward / backward-data bf16 layouts (wb may be null)
+    float *bias;                 // fp32 [coutp]
+};
+
+struct RelayoutArgs {
+    const float *params;
+    LayerDesc layer[4];
+};
+
+struct FeatureArgs {
+    const uint8_t *ir;  // left image
+    int pitch, W;
+    const uint16_t *s1, *s2;
+    const uint8_t *dint;
+    int max_disp;
+    float smax;
+    uint16_t *features;  // bf16 [P][8]
+    int64_t P;
+};
+
+struct CombineArgs {
+    const float *d2_sub, *out;
+    float *masked;
+    uint8_t *flags;
+    int64_t P;
+};
+
+hipError_t launch_conv(const ConvArgs &a, int cinp, int coutp, int epi, hipStream_t s);
+hipError_t launch_wgrad(const WgradArgs &a, int cinp, int coutp, int nblocks, int nbblocks, hipStream_t s);
+hipError_t launch_wgrad_reduce(const WgradReduceArgs &a, hipStream_t s);
+hipError_t launch_loss(const LossArgs &a, int nblocks, hipStream_t s);
+hipError_t launch_adam(const AdamArgs &a, hipStream_t s);
+hipError_t launch_relayout(const RelayoutArgs &a, hipStream_t s);
+hipError_t launch_features(const FeatureArgs &a, hipStream_t s);
+hipError_t launch_combine(const CombineArgs &a, hipStream_t s);
+hipError_t launch_targets(const float *d8_sub, const uint8_t *flags8, const float *d2_sub, float *t_res,
+                          uint8_t *t_valid, int64_t n, hipStream_t s);
+
+}  // namespace net
+}  // namespace ss

@@ -48,7 +48,7 @@ class Params(ct.Structure):
 class Outputs(ct.Structure):
     _fields_ = [(n, ct.c_void_p) for n in (
         "depth", "disp", "flags", "disp_int", "cost_best", "cost_second", "disp_right", "disp_sub",
-        "census_left", "census_right", "volume")]
+        "census_left", "census_right", "volume", "features")]
 
 
 _vp, _i32, _i64 = ct.c_void_p, ct.c_int32, ct.c_int64
@@ -161,7 +161,8 @@ class SimSense:
         self.compute(left, right, depth, disp, flags, stream)
         return depth, disp, flags
 
-    def compute_all(self, left: torch.Tensor, right: torch.Tensor, volume: bool = False, stream=None):
+    def compute_all(self, left: torch.Tensor, right: torch.Tensor, volume: bool = False, features: bool = False,
+                    stream=None):
         """Every intermediate of the path, as a dict of GPU tensors."""
         H, W = self.shape
         D = self.params["max_disp"]
@@ -180,6 +181,8 @@ class SimSense:
                    census_right=torch.empty((H, W), dtype=torch.int64, device=dev))
         if volume:
             out["volume"] = torch.empty((H, W, D), dtype=torch.int16, device=dev)
+        if features:
+            out["features"] = torch.empty((H, W, 8), dtype=torch.int16, device=dev)
         o = Outputs(**{k: v.data_ptr() for k, v in out.items()})
         _check(_lib.simsense_compute_ex(self._h, _ptr(left), _ptr(right), W, ct.byref(o), _stream(stream)),
                "simsense_compute_ex")
@@ -204,4 +207,116 @@ def census(params: Dict, img: torch.Tensor, stream=None) -> torch.Tensor:
     _need(img, torch.uint8, (H, W), "img")
     out = torch.empty((H, W), dtype=torch.int64, device=img.device)
     _check(_lib.simsense_census(ct.byref(p), _ptr(img), W, _ptr(out), _stream(stream)), "simsense_census")
+    return out
+
+
+# ---------------------------------------------------------------- learned surrogate
+_lib.simsense_net_num_params.restype = _i64
+_lib.simsense_net_create.argtypes = [_i64, ct.c_uint64, ct.POINTER(_vp)]
+_lib.simsense_net_destroy.argtypes = [_vp]
+_fp = ct.POINTER(ct.c_float)
+_lib.simsense_net_get_state.argtypes = [_vp, _fp, _fp, _fp, _i64, ct.POINTER(_i64)]
+_lib.simsense_net_set_state.argtypes = [_vp, _fp, _fp, _fp, _i64, _i64]
+_lib.simsense_net_get_grads.argtypes = [_vp, _fp, _i64]
+_lib.simsense_net_forward.argtypes = [_vp, _vp, _i32, _i32, _i32, _vp, _vp]
+_lib.simsense_net_train_step.argtypes = [_vp, _vp, _vp, _vp, _i32, _i32, _i32, ct.c_float, _vp, _vp]
+_lib.simsense_net_targets.argtypes = [_vp, _vp, _vp, _vp, _vp, _i64, _vp]
+_lib.simsense_learned_compute.argtypes = [_vp, _vp, _vp, _vp, _i32, ct.POINTER(Outputs), _vp]
+
+NUM_NET_PARAMS = int(_lib.simsense_net_num_params())
+
+
+def _host_f32(a):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a, a.ctypes.data_as(_fp)
+
+
+class Net:
+    """The learned surrogate's parameters, Adam state and device buffers."""
+
+    def __init__(self, max_pixels: int, seed: int = 0):
+        h = ct.c_void_p()
+        _check(_lib.simsense_net_create(int(max_pixels), int(seed), ct.byref(h)), "simsense_net_create")
+        self._h = h
+        self.max_pixels = int(max_pixels)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(_lib.simsense_net_destroy(self._h), "simsense_net_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_state(self):
+        import numpy as np
+        n = NUM_NET_PARAMS
+        p, m, v = (np.empty(n, np.float32) for _ in range(3))
+        step = _i64()
+        _check(_lib.simsense_net_get_state(self._h, p.ctypes.data_as(_fp), m.ctypes.data_as(_fp),
+                                           v.ctypes.data_as(_fp), n, ct.byref(step)), "simsense_net_get_state")
+        return p, m, v, int(step.value)
+
+    def set_state(self, params, m=None, v=None, step: int = 0):
+        p, pp = _host_f32(params)
+        mm = _host_f32(m) if m is not None else (None, None)
+        vv = _host_f32(v) if v is not None else (None, None)
+        _check(_lib.simsense_net_set_state(self._h, pp, mm[1], vv[1], NUM_NET_PARAMS, int(step)),
+               "simsense_net_set_state")
+
+    def get_grads(self):
+        import numpy as np
+        g = np.empty(NUM_NET_PARAMS, np.float32)
+        _check(_lib.simsense_net_get_grads(self._h, g.ctypes.data_as(_fp), NUM_NET_PARAMS), "simsense_net_get_grads")
+        return g
+
+    def forward(self, features: torch.Tensor, stream=None) -> torch.Tensor:
+        B, H, W, C = features.shape
+        if C != 8 or features.element_size() != 2 or not features.is_contiguous():
+            raise ValueError("features: contiguous 16-bit [B, H, W, 8] tensor (bf16 bits)")
+        out = torch.empty((B, H, W, 2), dtype=torch.float32, device=features.device)
+        _check(_lib.simsense_net_forward(self._h, _ptr(features), B, H, W, _ptr(out), _stream(stream)),
+               "simsense_net_forward")
+        return out
+
+    def train_step(self, features: torch.Tensor, t_res: torch.Tensor, t_valid: torch.Tensor, lr: float,
+                   stream=None) -> torch.Tensor:
+        B, H, W, C = features.shape
+        _need(t_res, torch.float32, (B, H, W), "t_res")
+        _need(t_valid, torch.uint8, (B, H, W), "t_valid")
+        loss = torch.empty(3, dtype=torch.float32, device=features.device)
+        _check(_lib.simsense_net_train_step(self._h, _ptr(features), _ptr(t_res), _ptr(t_valid), B, H, W,
+                                            float(lr), _ptr(loss), _stream(stream)), "simsense_net_train_step")
+        return loss
+
+
+def net_targets(d8_sub: torch.Tensor, flags8: torch.Tensor, d2_sub: torch.Tensor, stream=None):
+    t_res = torch.empty_like(d8_sub)
+    t_valid = torch.empty(d8_sub.shape, dtype=torch.uint8, device=d8_sub.device)
+    _check(_lib.simsense_net_targets(_ptr(d8_sub), _ptr(flags8), _ptr(d2_sub), _ptr(t_res), _ptr(t_valid),
+                                     d8_sub.numel(), _stream(stream)), "simsense_net_targets")
+    return t_res, t_valid
+
+
+def learned_compute(ss: "SimSense", net: Net, left: torch.Tensor, right: torch.Tensor, extras: bool = False,
+                    stream=None):
+    """The learned depth path on one pair: returns a dict of GPU tensors."""
+    H, W = ss.shape
+    dev = left.device
+    _need(left, torch.uint8, (H, W), "left")
+    _need(right, torch.uint8, (H, W), "right")
+    out = dict(depth=torch.empty((H, W), dtype=torch.float32, device=dev),
+               disp=torch.empty((H, W), dtype=torch.float32, device=dev),
+               flags=torch.empty((H, W), dtype=torch.uint8, device=dev))
+    if extras:
+        out.update(disp_sub=torch.empty((H, W), dtype=torch.float32, device=dev),
+                   disp_int=torch.empty((H, W), dtype=torch.uint8, device=dev),
+                   features=torch.empty((H, W, 8), dtype=torch.int16, device=dev))
+    o = Outputs(**{k: v.data_ptr() for k, v in out.items()})
+    _check(_lib.simsense_learned_compute(ss._h, net._h, _ptr(left), _ptr(right), W, ct.byref(o), _stream(stream)),
+           "simsense_learned_compute")
     return out
