@@ -35,6 +35,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the learned-form and batch legs")
+    ap.add_argument("--batch-pairs", type=int, default=256)
+    ap.add_argument("--fallback-frac", type=float, default=0.25,
+                    help="fall back to 8-path for a pair when this share of its logits is within (-tau, tau)")
+    ap.add_argument("--workers", type=int, default=12)
     ap.add_argument("--cpu-sample-rows", type=int, default=720,
                     help="rows of the 1280x720 pair the oracle times (full pair = 720)")
     return ap.parse_args()
@@ -54,12 +59,157 @@ def cpu_baseline(params, left, right, rows):
                       f"{dt:.2f} s single-threaded, scaled to pairs/s"}
 
 
+def _pool_generate(spec_seeds, workers):
+    from paper_2201_11924_amd.train import generate
+    return generate(spec_seeds, workers)
+
+
+def generate_batch_inputs(args):
+    """Host-side pair generation for the batch legs, in worker processes started
+    before this process touches the GPU."""
+    from synth import CONFIGS, pair_seed
+    from synth.stereo import c1_like
+    cfg = CONFIGS["c1"]
+    sensor = _pool_generate([(cfg["spec"], pair_seed(4, i)) for i in range(args.batch_pairs)], args.workers)
+    shapes = [(320, 240, 64), (640, 480, 96), (848, 480, 128), (1280, 720, 128)]
+    specs, plist = [], []
+    for si, (w, h, d) in enumerate(shapes):
+        c = c1_like(w, h, d)
+        for i in range(16):
+            specs.append((c["spec"], pair_seed(2, 16 * si + i)))
+            plist.append(c["params"])
+    uneven = _pool_generate(specs, args.workers)
+    return sensor, (uneven, plist)
+
+
+def learned_and_batch_legs(nat, args, out, inputs):
+    """The learned 2-path+net form against plain 8-path, and uneven batches."""
+    import torch
+    from paper_2201_11924_amd.train import load_checkpoint, metrics
+    from synth import CONFIGS, pair_seed
+    from synth.stereo import c1_like
+    cfg = CONFIGS["c1"]
+    params8 = cfg["params"]
+    params2 = dict(params8, num_paths=2)
+    W, H, D = params8["width"], params8["height"], params8["max_disp"]
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    ck = os.path.join(ROOT, "paper_2201_11924_amd", "weights", "surrogate_640x480_d128.ckpt")
+    chunk = 16
+    net = nat.Net(chunk * W * H, seed=0)
+    trained = os.path.exists(ck)
+    if trained:
+        load_checkpoint(ck, net)
+
+    # single pair, learned form
+    raw = inputs[0][0]
+    L = nat.ir_noise(t(raw[0]), t(raw[2]), t(raw[3]))
+    R = nat.ir_noise(t(raw[1]), t(raw[4]), t(raw[5]))
+    ss2 = nat.SimSense(params2)
+    for _ in range(10):
+        nat.learned_compute(ss2, net, L, R)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    reps = max(20, args.steps // 4)
+    for _ in range(reps):
+        nat.learned_compute(ss2, net, L, R)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_l = e0.elapsed_time(e1) / reps
+    ss2.close()
+    res = {"single_pair_2path_net": {"pairs_s": round(1000.0 / ms_l, 2), "ms": round(ms_l, 4)}}
+
+    # 256 pairs (32 cameras x 8 steps) of the sensor workload
+    npairs = args.batch_pairs
+    raws = inputs[0]
+    Ls, Rs = [], []
+    for r in raws:
+        Ls.append(nat.ir_noise(t(r[0]), t(r[2]), t(r[3])))
+        Rs.append(nat.ir_noise(t(r[1]), t(r[4]), t(r[5])))
+    del raws
+    torch.cuda.synchronize()
+    # plain 8-path in graph launches of 64 pairs
+    g8 = min(64, npairs)
+    b8 = nat.Batch([params8] * g8)
+    outs8 = [b8.outputs() for _ in range(0, npairs, g8)]
+    for i in range(0, npairs, g8):
+        b8.compute(Ls[i:i + g8], Rs[i:i + g8], outs8[i // g8])
+    torch.cuda.synchronize()
+    e0.record()
+    for i in range(0, npairs, g8):
+        b8.compute(Ls[i:i + g8], Rs[i:i + g8], outs8[i // g8])
+    e1.record()
+    torch.cuda.synchronize()
+    ms8 = e0.elapsed_time(e1)
+    b8.close()
+    # learned form, every pair in one graph launch
+    b2 = nat.Batch([params2] * npairs)
+    outs2 = b2.outputs()
+    unc = torch.zeros(npairs, dtype=torch.int32, device="cuda")
+    tau = 0.5
+    b2.learned_compute(net, Ls, Rs, outs2, tau, unc)
+    torch.cuda.synchronize()
+    e0.record()
+    b2.learned_compute(net, Ls, Rs, outs2, tau, unc)
+    e1.record()
+    torch.cuda.synchronize()
+    ms2 = e0.elapsed_time(e1)
+    # quality against 8-path, and the fallback decision per pair
+    frac_unsure = unc.cpu().numpy() / float(W * H)
+    fall = frac_unsure > args.fallback_frac
+    q = [metrics(outs2[i]["disp"].cpu().numpy(), outs8[i // g8][i % g8]["disp"].cpu().numpy())
+         for i in range(npairs)]
+    qm = {k: round(float(np.mean([m[k] for m in q])), 5) for k in q[0]}
+    qm_after = {k: round(float(np.mean([(m if not fall[i] else
+                                         metrics(outs8[i // g8][i % g8]["disp"].cpu().numpy(),
+                                                 outs8[i // g8][i % g8]["disp"].cpu().numpy()))[k]
+                                        for i, m in enumerate(q)])), 5) for k in q[0]}
+    pairs8 = npairs / (ms8 / 1000.0)
+    pairs2 = npairs / (ms2 / 1000.0)
+    res["batch_256_sensor"] = {
+        "pairs": npairs, "plain_8path_pairs_s": round(pairs8, 2), "learned_2path_net_pairs_s": round(pairs2, 2),
+        "speedup": round(pairs2 / pairs8, 3), "plain_graph_launches": (npairs + g8 - 1) // g8,
+        "learned_graph_launches": 1, "net_trained": trained,
+        "quality_vs_8path": qm, "fallback": {"tau": tau, "threshold_frac": args.fallback_frac,
+                                             "rate": round(float(fall.mean()), 4),
+                                             "quality_after_fallback": qm_after},
+        "learned_pairs_s_with_fallback_cost": round(npairs / (ms2 / 1000.0 + fall.sum() / pairs8), 2)}
+    b2.close()
+    net.close()
+    del Ls, Rs, outs2, outs8, raws
+    torch.cuda.empty_cache()
+
+    # 64 pairs of uneven sizes and disparity ranges in one graph launch, autotuned
+    raws, plist = inputs[1]
+    Ls = [nat.ir_noise(t(r[0]), t(r[2]), t(r[3])) for r in raws]
+    Rs = [nat.ir_noise(t(r[1]), t(r[4]), t(r[5])) for r in raws]
+    del raws
+    bu = nat.Batch(plist)
+    outs = bu.outputs()
+    best, cand = bu.autotune(Ls, Rs, outs, reps=3)
+    bu.compute(Ls, Rs, outs)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(5):
+        bu.compute(Ls, Rs, outs)
+    e1.record()
+    torch.cuda.synchronize()
+    msu = e0.elapsed_time(e1) / 5
+    work = sum(p["width"] * p["height"] * p["max_disp"] for p in plist)
+    res["batch_64_uneven"] = {"pairs_s": round(64 / (msu / 1000.0), 2), "ms_per_launch": round(msu, 3),
+                              "mpix_disp_per_s": round(work / (msu / 1000.0) / 1e6, 1), "tuning": best,
+                              "autotune_ms": [round(m, 3) for m in cand]}
+    bu.close()
+    out["learned_and_batches"] = res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    inputs = None if args.no_batch else generate_batch_inputs(args)
 
     import torch
     import paper_2201_11924_amd.native as nat
@@ -128,6 +278,9 @@ def main():
         "roofline": roofline,
     }
     ss.close()
+    if not args.no_batch:
+        learned_and_batch_legs(nat, args, out, inputs)
+        inputs = None
     if not args.no_cpu_baseline:
         from oracle import oracle as orc
         Lh = orc.ir_noise(pair.left, pair.gamma_l, pair.n_l)

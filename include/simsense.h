@@ -205,6 +205,64 @@ int simsense_net_targets(const float *d8_sub, const uint8_t *flags8, const float
 int simsense_learned_compute(simsense_handle *h, simsense_net *net, const uint8_t *left, const uint8_t *right,
                              int32_t pitch, const simsense_outputs *out, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Batches (a project addition): many pairs of uneven sizes and disparity
+ * ranges, as from many simulated cameras, computed by one graph launch.  Each
+ * pass of the path runs once over every pair; the aggregation pass is a
+ * persistent kernel that takes line blocks of all pairs from a queue, longest
+ * first.  The batch owns per-pair scratch like a handle (simsense_scratch_bytes
+ * of each pair's parameters).
+ * ---------------------------------------------------------------------- */
+typedef struct simsense_batch simsense_batch; /* opaque */
+
+/* One pair of a batch call: device pointers owned by the caller. */
+typedef struct simsense_pair {
+    const uint8_t *left, *right; /* rectified, noise-applied IR images */
+    int32_t pitch;               /* row stride in bytes, >= width */
+    float *depth;                /* required */
+    float *disp;                 /* nullable */
+    uint8_t *flags;              /* nullable */
+} simsense_pair;
+
+/* Launch shape of the batch kernels.
+ *  horizontal_lanes  lanes that hold one horizontal scanline's disparity vector:
+ *                    16, 32 or 64 (a quarter, half or whole wavefront), 0 = the
+ *                    default for each disparity range; pairs whose padded
+ *                    disparity count it does not divide keep their default.
+ *  blocks_per_cu     resident blocks per compute unit of the persistent
+ *                    aggregation kernel, 1..8. */
+typedef struct simsense_batch_tuning {
+    uint32_t struct_size;
+    int32_t horizontal_lanes;
+    int32_t blocks_per_cu;
+} simsense_batch_tuning;
+
+/* `params`: host array of n parameter sets (1 <= n <= 2048), one per pair slot;
+ * all must use the same census word width (<= 32 bits or > 32 bits). */
+int simsense_batch_create(const simsense_params *params, int32_t n, simsense_batch **out);
+int simsense_batch_destroy(simsense_batch *b);
+int64_t simsense_batch_scratch_bytes(const simsense_batch *b);
+/* `pairs`: host array of n entries, read during the call.  Asynchronous on `stream`. */
+int simsense_batch_compute(simsense_batch *b, const simsense_pair *pairs, void *stream);
+/* The learned form on a batch of equal-sized pairs (normally num_paths = 2): the
+ * batch's matching, then the net on chunks of as many pairs as the net's
+ * max_pixels allows, then disparity = d2_sub + residual where the logit is
+ * positive, then median and depth, all in one graph launch.  `uncertain`
+ * (device, n counters) receives per pair the number of pixels whose logit lies
+ * within (-tau, tau); a caller falls back to plain SGM for pairs where it is
+ * large.  The graph is kept for one (net, tau, uncertain) triple. */
+int simsense_batch_learned_compute(simsense_batch *b, simsense_net *net, const simsense_pair *pairs, float tau,
+                                   unsigned *uncertain, void *stream);
+int simsense_batch_set_tuning(simsense_batch *b, const simsense_batch_tuning *t);
+int simsense_batch_get_tuning(const simsense_batch *b, simsense_batch_tuning *t);
+/* Times every tuning candidate (horizontal_lanes in {16, 32, 64} x blocks_per_cu in
+ * {1, 2, 3, 4}) over `reps` launches on `pairs`, writes the mean milliseconds of
+ * candidate i to ms[i] (host, up to max_candidates) and their number to *count,
+ * keeps the fastest and returns it in *best.  Synchronous. */
+int simsense_batch_autotune(simsense_batch *b, const simsense_pair *pairs, int32_t reps,
+                            simsense_batch_tuning *best, float *ms, int32_t max_candidates, int32_t *count,
+                            void *stream);
+
 /* Human-readable name of a status code (static storage). */
 const char *simsense_strerror(int status);
 

@@ -1,507 +1,81 @@
-// Semi-global path aggregation (Sec. VI-D; the SGM recurrence of Hirschmueller,
-// which the paper cites):
-//   L_r(p,d) = C(p,d) + min(L_r(p-r,d), L_r(p-r,d+-1) + P1, m + P2) - m,
-//   m = min_k L_r(p-r,k),  C(p,d) = popcount(cL(p) ^ cR(p - d)).
-//
-// Every scanline of every direction is an independent sequence, so each one is
-// given to 16 lanes (one DPP row of a wave64) that hold its D-vector, dpl
-// consecutive disparities per lane.  A step of the recurrence is then:
-//   * the matching cost recomputed from census words held in LDS (XOR +
-//     popcount), so no cost volume is ever written;
-//   * the d-1 / d+1 neighbours from the lane's own registers, and at the lane
-//     edges through a row_shr / row_shl DPP move;
-//   * the path minimum m through a row_ror butterfly (4 DPP steps);
-// and the normalised state Q = L - m is kept in registers along the line.
-// With Q the update is L = C + min(Q(d), min(Q(d-1), Q(d+1)) + P1, P2), which
-// equals the recurrence above exactly; a line starts from Q = 0, which yields
-// L = C at its first pixel.
-//
-// A 256-thread block owns 16 lines of one direction and advances them by one
-// "clock" at a time.  Lines are grouped so that at every clock the block's 16
-// pixels lie in one image row and 16 consecutive columns (vertical lines, and
-// diagonals entering through the top/bottom row), or all in one column of 16
-// consecutive rows (horizontal lines).  Diagonals entering through a side column
-// are started one clock apart so they also share a row.  The census words a
-// block needs for 16 clocks are then a 16 x (Dpad + 31) word tile: it is loaded
-// from global memory while the previous 16 clocks are computed from the other
-// half of a double-buffered LDS tile, so the scanline loop waits on global
-// memory only once per 16 steps.
-//
-// Each direction writes its path values (<= bits + P2 <= 255) as bytes into a
-// buffer of its own, d fastest; the selection pass sums the directions.
+// Host side of the aggregation pass: work layout and dispatch to the
+// per-disparity-count instantiations (agg_dpl*.hip).
+#include <algorithm>
+
 #include "internal.h"
 
 namespace ss {
 
-namespace {
+constexpr int kChunkClocks = 16;  // clocks per census tile chunk (= lines of a row-sharing block)
 
-constexpr uint32_t kInf = 0x10000000u;      // outside the disparity range
-constexpr uint32_t kPadCost = 0x01000000u;  // cost of the padding disparities >= D
-constexpr int kChunk = 16;                  // clocks per LDS tile (= lines per block)
-static_assert(kChunk == kLinesPerBlock, "one tile slot per line");
-
-// DPP controls (GFX9 encoding)
-constexpr int kRowShl1 = 0x101, kRowShr1 = 0x111;
-constexpr int kRowRor1 = 0x121, kRowRor2 = 0x122, kRowRor4 = 0x124, kRowRor8 = 0x128;
-
-template <int CTRL>
-__device__ __forceinline__ uint32_t dpp_mov(uint32_t old, uint32_t v)
-{
-    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, 0xF, 0xF, false);
-}
-
-template <int CTRL>
-__device__ __forceinline__ uint32_t dpp_rot(uint32_t v)
-{
-    // a row rotation reads a valid lane for every lane, so no old value is needed
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, true);
-}
-
-// minimum over the 16 lanes of a DPP row, returned in every lane of the row
-__device__ __forceinline__ uint32_t row_min(uint32_t v)
-{
-    v = min(v, dpp_rot<kRowRor8>(v));
-    v = min(v, dpp_rot<kRowRor4>(v));
-    v = min(v, dpp_rot<kRowRor2>(v));
-    v = min(v, dpp_rot<kRowRor1>(v));
-    return v;
-}
-
-constexpr int kWaveShl1 = 0x130, kWaveShr1 = 0x138, kRowBcast15 = 0x142, kRowBcast31 = 0x143;
-
-// Cross-lane pieces of a line that spans LPL lanes (16: one DPP row, 32: half a
-// wave, 64: the whole wave).  Lanes hold consecutive disparity blocks.
-template <int LPL>
-struct LineOps {
-    // value of the previous lane (lane 0 of the line gets kInf)
-    static __device__ __forceinline__ uint32_t from_prev(uint32_t v, bool first)
-    {
-        if constexpr (LPL == 16) {
-            return dpp_mov<kRowShr1>(kInf, v);
-        } else {
-            const uint32_t r = dpp_mov<kWaveShr1>(kInf, v);
-            return LPL == 32 && first ? kInf : r;
-        }
-    }
-    // value of the next lane (the line's last lane gets kInf)
-    static __device__ __forceinline__ uint32_t from_next(uint32_t v, bool last)
-    {
-        if constexpr (LPL == 16) {
-            return dpp_mov<kRowShl1>(kInf, v);
-        } else {
-            const uint32_t r = dpp_mov<kWaveShl1>(kInf, v);
-            return LPL == 32 && last ? kInf : r;
-        }
-    }
-    // minimum over the line's lanes, in every lane of the line
-    static __device__ __forceinline__ uint32_t line_min(uint32_t v)
-    {
-        v = row_min(v);
-        if constexpr (LPL == 16) {
-            return v;
-        } else if constexpr (LPL == 32) {
-            // rows 1 and 3 take the minimum with lane 15 of the row before them
-            v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, kRowBcast15, 0xA, 0xF, false));
-            const uint32_t lo = __builtin_amdgcn_readlane(v, 31), hi = __builtin_amdgcn_readlane(v, 63);
-            return (threadIdx.x & 32) ? hi : lo;
-        } else {
-            v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, kRowBcast15, 0xA, 0xF, false));
-            v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, kRowBcast31, 0xC, 0xF, false));
-            return __builtin_amdgcn_readlane(v, 63);
-        }
-    }
-};
-
-template <bool WIDE>
-struct CensusWord;
-template <>
-struct CensusWord<false> {
-    using T = uint32_t;
-    static __device__ __forceinline__ uint32_t hamming(T a, T b) { return __popc(a ^ b); }
-};
-template <>
-struct CensusWord<true> {
-    using T = uint64_t;
-    static __device__ __forceinline__ uint32_t hamming(T a, T b) { return __popcll(a ^ b); }
-};
-
-template <int DPL>
-__device__ __forceinline__ void store_bytes(uint8_t *dst, const uint32_t (&L)[DPL])
-{
-    if constexpr (DPL % 4 == 0) {
-        uint32_t w[DPL / 4];
-#pragma unroll
-        for (int k = 0; k < DPL / 4; ++k) {
-            // low bytes of L0..L3 into one word: two byte-pair gathers, then one merge
-            const uint32_t lo = __builtin_amdgcn_perm(L[4 * k + 1], L[4 * k], 0x0c0c0400u);
-            const uint32_t hi = __builtin_amdgcn_perm(L[4 * k + 3], L[4 * k + 2], 0x0c0c0400u);
-            w[k] = __builtin_amdgcn_perm(hi, lo, 0x05040100u);
-        }
-        if constexpr (DPL == 4) {
-            *(uint32_t *)dst = w[0];
-        } else if constexpr (DPL == 8) {
-            *(uint2 *)dst = make_uint2(w[0], w[1]);
-        } else if constexpr (DPL == 12) {
-            *(uint2 *)dst = make_uint2(w[0], w[1]);
-            *(uint32_t *)(dst + 8) = w[2];
-        } else {
-            static_assert(DPL == 16, "unsupported disparities per lane");
-            *(uint4 *)dst = make_uint4(w[0], w[1], w[2], w[3]);
-        }
-    } else if constexpr (DPL % 2 == 0) {
-#pragma unroll
-        for (int k = 0; k < DPL / 2; ++k)
-            *(uint16_t *)(dst + 2 * k) = (uint16_t)((L[2 * k] & 0xFF) | ((L[2 * k + 1] & 0xFF) << 8));
-    } else {
-#pragma unroll
-        for (int k = 0; k < DPL; ++k) dst[k] = (uint8_t)L[k];
-    }
-}
-
-// s_waitcnt immediate that waits for vmcnt <= n and leaves the other counters
-// alone (GFX9 encoding: vmcnt[3:0] | expcnt[6:4] | lgkmcnt[11:8] | vmcnt_hi[15:14])
-__host__ __device__ constexpr int vmcnt_encoding(int n)
-{
-    // counts above the 6-bit maximum wait for more than needed, which is safe
-    return n > 63 ? vmcnt_encoding(63) : (n & 0xF) | (0x7 << 4) | (0xF << 8) | (((n >> 4) & 0x3) << 14);
-}
-
-// global store instructions store_bytes issues per step
-template <int DPL>
-__host__ __device__ constexpr int store_ops()
-{
-    return DPL % 4 == 0 ? (DPL == 12 ? 2 : 1) : (DPL % 2 == 0 ? DPL / 2 : DPL);
-}
-
-// Geometry of one block of 16 lines of one direction.
-//  kind 0: horizontal; the 16 lines are rows r0..r0+15 and every line is at
-//          column xs + t*dx at clock t;
-//  kind 1: vertical, or diagonal entering through the top/bottom row ye: line i
-//          starts at column g0 + i; at clock t every line is in row ye + t*dy and
-//          line i in column g0 + t*dx + i;
-//  kind 2: diagonal entering through the side column xe: line i starts at row
-//          ye + dy*(j0 + i + 1) and runs one clock behind line i-1, so at clock t
-//          every line is in row ye + dy*(j0 + 1 + t).
-struct BlockGeom {
-    int kind, dx, dy;
-    int r0, g0, j0;
-    int xs, xe, ye;
-    int clocks;  // clocks the block runs
-    int nvalid;  // lines of the block that exist
-};
-
-__device__ __forceinline__ BlockGeom block_geometry(int dx, int dy, int blk, int W, int H, int hlines)
-{
-    BlockGeom g{};
-    g.dx = dx;
-    g.dy = dy;
-    g.ye = dy > 0 ? 0 : H - 1;
-    g.xe = dx > 0 ? 0 : W - 1;
-    if (dy == 0) {
-        g.kind = 0;
-        g.r0 = blk * hlines;
-        g.xs = dx > 0 ? 0 : W - 1;
-        g.clocks = W;
-        g.nvalid = min(hlines, H - g.r0);
-    } else {
-        const int top_blocks = (W + kChunk - 1) / kChunk;
-        if (dx == 0 || blk < top_blocks) {
-            g.kind = 1;
-            g.g0 = blk * kChunk;
-            g.nvalid = min(kChunk, W - g.g0);
-            if (dx == 0) {
-                g.clocks = H;
-            } else {
-                // the longest line of the block starts farthest from its exit column
-                const int lfirst = dx > 0 ? W - g.g0 : g.g0 + 1;
-                const int llast = dx > 0 ? W - (g.g0 + g.nvalid - 1) : g.g0 + g.nvalid;
-                g.clocks = min(max(lfirst, llast), H);
-            }
-        } else {
-            g.kind = 2;
-            g.j0 = (blk - top_blocks) * kChunk;
-            g.nvalid = min(kChunk, H - 1 - g.j0);
-            int c = 0;  // line i: skew i, length min(W, H - j0 - i - 1)
-            for (int i = 0; i < g.nvalid; ++i) c = max(c, i + min(W, H - g.j0 - i - 1));
-            g.clocks = c;
-        }
-    }
-    return g;
-}
-
-// row and leftmost column of the block's 16-column window at clock t (kinds 1, 2)
-__device__ __forceinline__ void window_at(const BlockGeom &g, int t, int &row, int &xm)
-{
-    if (g.kind == 1) {
-        row = g.ye + t * g.dy;
-        xm = g.g0 + t * g.dx;
-    } else {
-        row = g.ye + g.dy * (g.j0 + 1 + t);
-        xm = g.dx > 0 ? g.xe + t - (kChunk - 1) : g.xe - t;
-    }
-}
-
-}  // namespace
-
-// One block's scanlines.  HORIZ selects the horizontal layout (kind 0);
-// otherwise the block is of kind 1 or 2, whose lines share one image row per
-// clock: row(t) = row0 + t*dy, leftmost column xm(t) = xm0 + t*dx, lane column
-// xm(t) + xlane.  LPL lanes hold one line, DPL disparities each (LPL * DPL = Dpad).
-//
-// Census tiles move global -> LDS with direct-to-LDS loads into a ring of three
-// tile buffers, two chunks ahead of the chunk being computed; every lane of a
-// wave writes 4 consecutive bytes, so the tile is filled as a flat array of
-// dwords (two per word when census words are 64-bit).
-//
-// A kind-2 line that has not started yet (clock < its skew) is fed zero cost:
-// from Q = 0 the recurrence then yields L = 0 and m = 0, so Q stays 0 until the
-// line's first pixel, exactly the state a line starts from.  Lanes of lines that
-// have ended (or not started) store into one spare pixel after the image, so
-// every step issues the same unconditional store.
-template <int DPL, int LPL, bool WIDE, bool HORIZ, int TILE>
-__device__ __forceinline__ void run_lines(const AggregateArgs &a, const BlockGeom &g, uint8_t *__restrict__ out,
-                                          uint32_t (*tile)[TILE])
-{
-    using CW = CensusWord<WIDE>;
-    using LO = LineOps<LPL>;
-    using Word = typename CW::T;
-    constexpr int kWordDw = WIDE ? 2 : 1;                // dwords per census word
-    constexpr int kDpad = LPL * DPL;
-    constexpr int kLines = kBlock / LPL;                 // lines per block
-    constexpr int kSlots = HORIZ ? kLines : kChunk;      // tile slots: lines or clocks
-    constexpr int kSlot = kDpad + 2 * kChunk - 1;        // cR window (Dpad + 15) then cL window (16)
-    constexpr int kTileDw = kSlots * kSlot * kWordDw;
-    constexpr int kLoads = (kTileDw + kBlock - 1) / kBlock;
-    static_assert(HORIZ || LPL == kLanesPerLine, "row-sharing lines use one DPP row per line");
-    static_assert(kLoads * kBlock <= TILE, "tile too small");
-    const int W = a.W, H = a.H, D = a.D;
-    const int lane = threadIdx.x % LPL, li = threadIdx.x / LPL;
-    const bool first = lane == 0, last = lane == LPL - 1;
-    const int d0 = lane * DPL;
-    const uint32_t *__restrict__ cl = (const uint32_t *)a.census_l;
-    const uint32_t *__restrict__ cr = (const uint32_t *)a.census_r;
-    const uint32_t p1 = a.p1, p2 = a.p2, bits = a.bits;
-    const bool padded = D < kDpad;
-    const size_t trash = (size_t)W * H * kDpad + d0;
-
-    // per-block line layout
-    int row0 = 0, xm0 = 0, xlane = 0, len = 0, skew = 0;
-    if (HORIZ) {
-        if (li < g.nvalid) len = W;
-    } else if (g.kind == 1) {
-        row0 = g.ye;
-        xm0 = g.g0;
-        xlane = li;
-        if (li < g.nvalid) {
-            const int x0 = g.g0 + li;
-            len = g.dx == 0 ? H : min(g.dx > 0 ? W - x0 : x0 + 1, H);
-        }
-    } else {
-        row0 = g.ye + g.dy * (g.j0 + 1);
-        xm0 = g.dx > 0 ? g.xe - (kChunk - 1) : g.xe;
-        xlane = g.dx > 0 ? kChunk - 1 - li : li;
-        skew = li;
-        if (li < g.nvalid) len = min(W, H - g.j0 - li - 1);
-    }
-    const bool skewed = !HORIZ && g.kind == 2;
-
-    // row and leftmost column of the 16-column window of tile slot `slot` of the
-    // chunk that starts at clock c0
-    auto slot_window = [&](int c0, int slot, int &row, int &xm) {
-        if (HORIZ) {
-            row = g.r0 + slot;
-            const int xc = g.xs + c0 * g.dx;
-            xm = g.dx > 0 ? xc : xc - (kChunk - 1);
-        } else {
-            row = row0 + (c0 + slot) * g.dy;
-            xm = xm0 + (c0 + slot) * g.dx;
-        }
-    };
-    // direct-to-LDS loads of the chunk starting at clock c0 into ring buffer buf
-    auto stage = [&](int c0, int buf) {
-#pragma unroll
-        for (int k = 0; k < kLoads; ++k) {
-            const int e = threadIdx.x + k * kBlock;  // dword of the tile
-            const int q = e / kWordDw, h = e - q * kWordDw;
-            const int qc = q < kSlots * kSlot ? q : kSlots * kSlot - 1;
-            const int slot = qc / kSlot, idx = qc - slot * kSlot;
-            int row, xm;
-            slot_window(c0, slot, row, xm);
-            const bool is_left = idx >= kDpad + kChunk - 1;
-            int col = is_left ? xm + idx - (kDpad + kChunk - 1) : xm - kDpad + 1 + idx;
-            row = min(max(row, 0), H - 1);
-            col = min(max(col, 0), W - 1);
-            const uint32_t *src = (is_left ? cl : cr) + ((size_t)row * W + col) * kWordDw + h;
-            __builtin_amdgcn_global_load_lds(src, &tile[buf][k * kBlock + (threadIdx.x & ~63)], 4, 0, 0);
-        }
-    };
-    // lane's pixel, tile slot and window at clock c0 + k
-    auto locate = [&](int c0, int k, int &x, int &row, int &xm, int &slot) {
-        const int t = c0 + k;
-        slot = HORIZ ? li : k;
-        slot_window(c0, slot, row, xm);
-        x = HORIZ ? g.xs + t * g.dx : xm + xlane;
-    };
-    // census words of one clock: cL(x) and cR(x - d) for d = d0 + DPL - 1 .. d0
-    auto fetch = [&](int buf, int slot, int xo, Word &wl, Word(&wr)[DPL]) {
-        const Word *sl = (const Word *)&tile[buf][0] + slot * kSlot;
-        wl = sl[kDpad + kChunk - 1 + xo];
-        const Word *p = sl + (xo + kDpad - d0 - DPL);
-#pragma unroll
-        for (int j = 0; j < DPL; ++j) wr[j] = p[j];
-    };
-
-    uint32_t Q[DPL];
-#pragma unroll
-    for (int j = 0; j < DPL; ++j) Q[j] = 0;
-
-    const int nchunks = (g.clocks + kChunk - 1) / kChunk;
-    stage(0, 0);
-    if (nchunks > 1) stage(kChunk, 1);
-    // chunk 0 must be in LDS: at most chunk 1's loads may still be in flight
-    if (nchunks > 1) __builtin_amdgcn_s_waitcnt(vmcnt_encoding(kLoads));
-    else __builtin_amdgcn_s_waitcnt(vmcnt_encoding(0));
-    __syncthreads();
-
-    for (int c = 0; c < nchunks; ++c) {
-        const int buf = c % 3;
-        const int c0 = c * kChunk;
-        const bool ahead = c + 2 < nchunks;
-        if (ahead) stage(c0 + 2 * kChunk, (c + 2) % 3);
-        Word wl_n, wr_n[DPL];
-        {
-            int x, row, xm, slot;
-            locate(c0, 0, x, row, xm, slot);
-            fetch(buf, slot, x - xm, wl_n, wr_n);
-        }
-#pragma unroll
-        for (int k = 0; k < kChunk; ++k) {
-            const int t = c0 + k;
-            const int s = t - skew;
-            int x, row, xm, slot;
-            locate(c0, k, x, row, xm, slot);
-            const Word wl = wl_n;
-            Word wr[DPL];
-#pragma unroll
-            for (int j = 0; j < DPL; ++j) wr[j] = wr_n[j];
-            if (k + 1 < kChunk) {
-                // next clock's census words are read while this clock computes
-                int xn, rown, xmn, slotn;
-                locate(c0, k + 1, xn, rown, xmn, slotn);
-                fetch(buf, slotn, xn - xmn, wl_n, wr_n);
-            }
-            const bool active = s >= 0 && s < len;
-            const uint32_t qm_edge = LO::from_prev(Q[DPL - 1], first);
-            const uint32_t qp_edge = LO::from_next(Q[0], last);
-            uint32_t L[DPL];
-            uint32_t m = 0xFFFFFFFFu;
-            // the block's leftmost column decides whether any lane sees x - d < 0;
-            // the first chunk of skewed lines has lines that have not started
-            const bool border = padded || (HORIZ ? x : xm) < kDpad - 1 || (skewed && c == 0);
-            if (!border) {
-#pragma unroll
-                for (int j = 0; j < DPL; ++j) {
-                    const uint32_t qm = j > 0 ? Q[j - 1] : qm_edge;
-                    const uint32_t qp = j < DPL - 1 ? Q[j + 1] : qp_edge;
-                    const uint32_t tt = min(min(Q[j], min(qm, qp) + p1), p2);
-                    L[j] = tt + CW::hamming(wl, wr[DPL - 1 - j]);
-                    m = min(m, L[j]);
-                }
-            } else {
-#pragma unroll
-                for (int j = 0; j < DPL; ++j) {
-                    const int d = d0 + j;
-                    const uint32_t cst = CW::hamming(wl, wr[DPL - 1 - j]);
-                    uint32_t C = d < D ? (x - d >= 0 ? cst : bits) : kPadCost;
-                    C = s < 0 ? 0u : C;
-                    const uint32_t qm = j > 0 ? Q[j - 1] : qm_edge;
-                    const uint32_t qp = j < DPL - 1 ? Q[j + 1] : qp_edge;
-                    const uint32_t tt = min(min(Q[j], min(qm, qp) + p1), p2);
-                    L[j] = tt + C;
-                    m = min(m, L[j]);
-                }
-            }
-            m = LO::line_min(m);
-#pragma unroll
-            for (int j = 0; j < DPL; ++j) Q[j] = L[j] - m;
-            const size_t o = active ? ((size_t)row * W + x) * kDpad + d0 : trash;
-            store_bytes<DPL>(out + o, L);
-        }
-        // the next chunk's tile must have landed: only this chunk's look-ahead
-        // loads and its kChunk stores may still be in flight.  The tile is written
-        // by the loads themselves, so a bare s_barrier (no release fence, which
-        // would also wait for every global store) orders the waves; the empty asm
-        // statements keep the compiler from moving LDS reads across it.
-        if (ahead) __builtin_amdgcn_s_waitcnt(vmcnt_encoding(kLoads + store_ops<DPL>() * kChunk));
-        else __builtin_amdgcn_s_waitcnt(vmcnt_encoding(0));
-        asm volatile("" ::: "memory");
-        __builtin_amdgcn_s_barrier();
-        asm volatile("" ::: "memory");
-    }
-}
-
-template <int DPL, bool WIDE>
-__global__ __launch_bounds__(kBlock) void aggregate_kernel(AggregateArgs a)
-{
-    constexpr int kDpad = kLanesPerLine * DPL;
-    constexpr int kHL = horizontal_lanes(kDpad);
-    constexpr int kTileDw = kChunk * (kDpad + 2 * kChunk - 1) * (WIDE ? 2 : 1);
-    constexpr int kTile = (kTileDw + kBlock - 1) / kBlock * kBlock;
-    __shared__ uint32_t tile[3][kTile];
-    int dir = 0;
-#pragma unroll
-    for (int k = 1; k < 8; ++k)
-        if (k < a.ndirs && (int)blockIdx.x >= a.block_begin[k]) dir = k;
-    const BlockGeom g = block_geometry(a.dx[dir], a.dy[dir], (int)blockIdx.x - a.block_begin[dir], a.W, a.H,
-                                       kBlock / kHL);
-    uint8_t *out = a.out[dir];
-    if (g.kind == 0) {
-        // horizontal lines are the longest dependency chains of the pass: more
-        // lanes per line to shorten each step, and issue priority
-        __builtin_amdgcn_s_setprio(2);
-        run_lines<kDpad / kHL, kHL, WIDE, true, kTile>(a, g, out, tile);
-    } else {
-        run_lines<DPL, kLanesPerLine, WIDE, false, kTile>(a, g, out, tile);
-    }
-}
+hipError_t launch_agg_dpl1(const AggregateArgs *a, const AggregateQueue *q, int grid, int hl, bool wide, hipStream_t s);
+hipError_t launch_agg_dpl2(const AggregateArgs *a, const AggregateQueue *q, int grid, int hl, bool wide, hipStream_t s);
+hipError_t launch_agg_dpl4(const AggregateArgs *a, const AggregateQueue *q, int grid, int hl, bool wide, hipStream_t s);
+hipError_t launch_agg_dpl6(const AggregateArgs *a, const AggregateQueue *q, int grid, int hl, bool wide, hipStream_t s);
+hipError_t launch_agg_dpl8(const AggregateArgs *a, const AggregateQueue *q, int grid, int hl, bool wide, hipStream_t s);
+hipError_t launch_agg_dpl12(const AggregateArgs *a, const AggregateQueue *q, int grid, int hl, bool wide, hipStream_t s);
+hipError_t launch_agg_dpl16(const AggregateArgs *a, const AggregateQueue *q, int grid, int hl, bool wide, hipStream_t s);
 
 namespace {
-template <int DPL>
-hipError_t launch_agg_dpl(const AggregateArgs &a, bool wide, hipStream_t s)
+hipError_t launch_agg(const AggregateArgs *a, const AggregateQueue *q, int grid, int dpad, int hl, bool wide,
+                      hipStream_t s)
 {
-    dim3 grid(a.block_begin[a.ndirs]), block(kBlock);
-    if (wide)
-        hipLaunchKernelGGL((aggregate_kernel<DPL, true>), grid, block, 0, s, a);
-    else
-        hipLaunchKernelGGL((aggregate_kernel<DPL, false>), grid, block, 0, s, a);
-    return hipGetLastError();
-}
-}  // namespace
-
-int aggregate_blocks(int dx, int dy, int W, int H, int dpad)
-{
-    if (dy == 0) {
-        const int lines = kBlock / horizontal_lanes(dpad);
-        return (H + lines - 1) / lines;
-    }
-    const int top = (W + kChunk - 1) / kChunk;
-    if (dx == 0) return top;
-    return top + (H - 1 + kChunk - 1) / kChunk;
-}
-
-hipError_t launch_aggregate(const AggregateArgs &a, bool wide, hipStream_t s)
-{
-    if (a.block_begin[a.ndirs] == 0) return hipSuccess;
-    switch (a.Dpad / kLanesPerLine) {
-    case 1: return launch_agg_dpl<1>(a, wide, s);
-    case 2: return launch_agg_dpl<2>(a, wide, s);
-    case 4: return launch_agg_dpl<4>(a, wide, s);
-    case 6: return launch_agg_dpl<6>(a, wide, s);
-    case 8: return launch_agg_dpl<8>(a, wide, s);
-    case 12: return launch_agg_dpl<12>(a, wide, s);
-    case 16: return launch_agg_dpl<16>(a, wide, s);
+    switch (dpad / kLanesPerLine) {
+    case 1: return launch_agg_dpl1(a, q, grid, hl, wide, s);
+    case 2: return launch_agg_dpl2(a, q, grid, hl, wide, s);
+    case 4: return launch_agg_dpl4(a, q, grid, hl, wide, s);
+    case 6: return launch_agg_dpl6(a, q, grid, hl, wide, s);
+    case 8: return launch_agg_dpl8(a, q, grid, hl, wide, s);
+    case 12: return launch_agg_dpl12(a, q, grid, hl, wide, s);
+    case 16: return launch_agg_dpl16(a, q, grid, hl, wide, s);
     default: return hipErrorInvalidValue;
     }
+}
+}  // namespace
+
+bool horizontal_lanes_valid(int dpad, int hl)
+{
+    return (hl == 16 || hl == 32 || hl == 64) && dpad % hl == 0;
+}
+
+int aggregate_blocks(int dx, int dy, int W, int H, int hl)
+{
+    if (dy == 0) {
+        const int lines = kBlock / hl;
+        return (H + lines - 1) / lines;
+    }
+    const int top = (W + kChunkClocks - 1) / kChunkClocks;
+    if (dx == 0) return top;
+    return top + (H - 1 + kChunkClocks - 1) / kChunkClocks;
+}
+
+int aggregate_block_clocks(int dx, int dy, int blk, int W, int H, int hl)
+{
+    if (dy == 0) return W;
+    const int top = (W + kChunkClocks - 1) / kChunkClocks;
+    if (dx == 0) return H;
+    if (blk < top) {
+        const int g0 = blk * kChunkClocks, nvalid = std::min(kChunkClocks, W - g0);
+        const int lfirst = dx > 0 ? W - g0 : g0 + 1;
+        const int llast = dx > 0 ? W - (g0 + nvalid - 1) : g0 + nvalid;
+        return std::min(std::max(lfirst, llast), H);
+    }
+    const int j0 = (blk - top) * kChunkClocks, nvalid = std::min(kChunkClocks, H - 1 - j0);
+    int c = 0;
+    for (int i = 0; i < nvalid; ++i) c = std::max(c, i + std::min(W, H - j0 - i - 1));
+    return c;
+}
+
+hipError_t launch_aggregate(const AggregateArgs &a, bool wide, int hl, hipStream_t s)
+{
+    if (a.block_begin[a.ndirs] == 0) return hipSuccess;
+    return launch_agg(&a, nullptr, 0, a.Dpad, hl, wide, s);
+}
+
+hipError_t launch_aggregate_queue(const AggregateQueue &q, int dpad, bool wide, int hl, int grid, hipStream_t s)
+{
+    if (q.nitems == 0) return hipSuccess;
+    return launch_agg(nullptr, &q, grid, dpad, hl, wide, s);
 }
 
 }  // namespace ss

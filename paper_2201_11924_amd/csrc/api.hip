@@ -152,10 +152,10 @@ int enqueue_match(simsense_handle *h, const uint8_t *left, const uint8_t *right,
         ag.dx[r] = kPathDx[r];
         ag.dy[r] = kPathDy[r];
         ag.out[r] = h->paths[r];
-        ag.block_begin[r + 1] = ag.block_begin[r] + aggregate_blocks(kPathDx[r], kPathDy[r], W, H, h->Dpad);
+        ag.block_begin[r + 1] = ag.block_begin[r] + aggregate_blocks(kPathDx[r], kPathDy[r], W, H, h->hlanes);
     }
     profile_mark(h, SIMSENSE_PASS_AGGREGATE, false, s);
-    SS_TRY(launch_aggregate(ag, h->wide, s));
+    SS_TRY(launch_aggregate(ag, h->wide, h->hlanes, s));
     profile_mark(h, SIMSENSE_PASS_AGGREGATE, true, s);
 
     SelectArgs sa{};
@@ -225,6 +225,7 @@ int simsense_create(const simsense_params *params, simsense_handle **out)
     h->bits = census_bits(params->census_w, params->census_h, params->census_mode);
     h->wide = h->bits > 32;
     h->Dpad = padded_disp(params->max_disp);
+    h->hlanes = horizontal_lanes(h->Dpad);
     h->ndirs = params->num_paths;
     if (hipMalloc(&h->block, l.total) != hipSuccess) {
         (void)hipGetLastError();

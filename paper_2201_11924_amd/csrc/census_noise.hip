@@ -40,14 +40,12 @@ hipError_t launch_ir_noise(const uint8_t *in, const float *gamma, const float *n
 constexpr int kCensusTx = 32, kCensusTy = 8;
 
 template <typename Word>
-__global__ __launch_bounds__(256) void census_kernel(const uint8_t *__restrict__ img, int pitch, int W,
-                                                     int H, int cw, int ch, int mode,
-                                                     Word *__restrict__ out)
+__device__ __forceinline__ void census_tile(const uint8_t *__restrict__ img, int pitch, int W, int H, int cw, int ch,
+                                            int mode, Word *__restrict__ out, int bx, int by, uint8_t *tile)
 {
-    extern __shared__ uint8_t tile[];
     const int rw = cw / 2, rh = ch / 2;
     const int tw = kCensusTx + cw - 1, th = kCensusTy + ch - 1;
-    const int x0 = blockIdx.x * kCensusTx - rw, y0 = blockIdx.y * kCensusTy - rh;
+    const int x0 = bx * kCensusTx - rw, y0 = by * kCensusTy - rh;
     const int tid = threadIdx.y * kCensusTx + threadIdx.x;
     for (int i = tid; i < tw * th; i += kCensusTx * kCensusTy) {
         int ty = i / tw, tx = i - ty * tw;
@@ -55,7 +53,7 @@ __global__ __launch_bounds__(256) void census_kernel(const uint8_t *__restrict__
         tile[i] = img[(size_t)gy * pitch + gx];
     }
     __syncthreads();
-    const int x = blockIdx.x * kCensusTx + threadIdx.x, y = blockIdx.y * kCensusTy + threadIdx.y;
+    const int x = bx * kCensusTx + threadIdx.x, y = by * kCensusTy + threadIdx.y;
     if (x >= W || y >= H) return;
     // window centre inside the tile
     const int cx = threadIdx.x + rw, cy = threadIdx.y + rh;
@@ -83,6 +81,38 @@ __global__ __launch_bounds__(256) void census_kernel(const uint8_t *__restrict__
     }
     out[(size_t)y * W + x] = word;
 }
+
+template <typename Word>
+__global__ __launch_bounds__(256) void census_kernel(const uint8_t *__restrict__ img, int pitch, int W, int H, int cw,
+                                                     int ch, int mode, Word *__restrict__ out)
+{
+    extern __shared__ uint8_t tile[];
+    census_tile<Word>(img, pitch, W, H, cw, ch, mode, out, blockIdx.x, blockIdx.y, tile);
+}
+
+// batch form: one block per (job, 32x8 tile) item; tile = by * ceil(W/32) + bx
+template <typename Word>
+__global__ __launch_bounds__(256) void census_batch_kernel(CensusBatch b)
+{
+    extern __shared__ uint8_t tile[];
+    const uint32_t it = b.items[blockIdx.x];
+    const CensusJob &j = b.jobs[it >> 20];
+    const int t = (int)(it & 0xFFFFFu), tx = (j.W + kCensusTx - 1) / kCensusTx;
+    census_tile<Word>(j.img, j.pitch, j.W, j.H, j.cw, j.ch, j.mode, (Word *)j.out, t % tx, t / tx, tile);
+}
+
+hipError_t launch_census_batch(const CensusBatch &b, bool out64, hipStream_t s)
+{
+    if (b.nitems == 0) return hipSuccess;
+    const size_t lds = (size_t)(kCensusTx + b.max_cw - 1) * (kCensusTy + b.max_ch - 1);
+    if (out64)
+        hipLaunchKernelGGL(census_batch_kernel<uint64_t>, dim3(b.nitems), dim3(kCensusTx, kCensusTy), lds, s, b);
+    else
+        hipLaunchKernelGGL(census_batch_kernel<uint32_t>, dim3(b.nitems), dim3(kCensusTx, kCensusTy), lds, s, b);
+    return hipGetLastError();
+}
+
+int census_tiles(int W, int H) { return ((W + kCensusTx - 1) / kCensusTx) * ((H + kCensusTy - 1) / kCensusTy); }
 
 hipError_t launch_census(const uint8_t *img, int pitch, int W, int H, int cw, int ch, int mode, void *out,
                          bool out64, hipStream_t s)

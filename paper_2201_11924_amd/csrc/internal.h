@@ -24,11 +24,13 @@ int census_bits(int cw, int ch, int mode);
 extern const int kPathDx[8];
 extern const int kPathDy[8];
 int path_lines(int dx, int dy, int W, int H);
-// Lanes per horizontal line: horizontal lines are the longest chains of the
-// aggregation, so they are spread over more lanes (fewer instructions per step).
+// Default lanes per horizontal line: horizontal lines are the longest chains of
+// the aggregation, so they are spread over more lanes (fewer instructions per step).
 constexpr int horizontal_lanes(int dpad) { return dpad % 64 == 0 ? 64 : (dpad % 32 == 0 ? 32 : 16); }
-// blocks the aggregation kernel launches for one direction
-int aggregate_blocks(int dx, int dy, int W, int H, int dpad);
+bool horizontal_lanes_valid(int dpad, int hl);
+// blocks of work of one direction, and the clocks block `blk` runs
+int aggregate_blocks(int dx, int dy, int W, int H, int hl);
+int aggregate_block_clocks(int dx, int dy, int blk, int W, int H, int hl);
 
 struct AggregateArgs {
     const void *census_l, *census_r;  // uint32 words, or uint64 when bits > 32
@@ -68,9 +70,43 @@ hipError_t launch_ir_noise(const uint8_t *in, const float *gamma, const float *n
                            int64_t count, hipStream_t s);
 hipError_t launch_census(const uint8_t *img, int pitch, int W, int H, int cw, int ch, int mode,
                          void *out, bool out64, hipStream_t s);
-hipError_t launch_aggregate(const AggregateArgs &a, bool wide, hipStream_t s);
+struct AggregateQueue {
+    const AggregateArgs *slots;  // per pair slot (device)
+    const uint32_t *items;       // slot << 20 | block, longest first (device)
+    int nitems;
+    unsigned *counter;           // zero before the launch
+};
+hipError_t launch_aggregate(const AggregateArgs &a, bool wide, int hl, hipStream_t s);
+hipError_t launch_aggregate_queue(const AggregateQueue &q, int dpad, bool wide, int hl, int grid, hipStream_t s);
 hipError_t launch_select(const SelectArgs &a, hipStream_t s);
 hipError_t launch_post(const PostArgs &a, hipStream_t s);
+
+// batched forms: per-slot arguments in device memory, one block per item
+// (slot << 20 | index), items in device memory
+struct CensusJob {
+    const uint8_t *img;
+    int pitch, W, H, cw, ch, mode;
+    void *out;
+};
+struct CensusBatch {
+    const CensusJob *jobs;
+    const uint32_t *items;
+    int nitems, max_cw, max_ch;
+};
+struct SelectBatch {
+    const SelectArgs *slots;
+    const uint32_t *items;  // slot << 20 | row
+    int nitems, max_width;
+};
+struct PostBatch {
+    const PostArgs *slots;
+    const uint32_t *items;  // slot << 20 | tile (64x4 tiles, row-major)
+    int nitems;
+};
+hipError_t launch_census_batch(const CensusBatch &b, bool out64, hipStream_t s);
+hipError_t launch_select_batch(const SelectBatch &b, int dpad, int ndirs, bool small, hipStream_t s);
+hipError_t launch_post_batch(const PostBatch &b, hipStream_t s);
+int census_tiles(int W, int H);
 struct PathSet {
     const uint8_t *p[8];
 };
@@ -94,6 +130,7 @@ void profile_mark(simsense_handle *h, int pass, bool end, hipStream_t s);
 struct simsense_handle {  // opaque to callers
     simsense_params p;
     int bits, Dpad, ndirs;
+    int hlanes;  // lanes per horizontal scanline
     bool wide;
     void *block;
     void *census_l, *census_r;

@@ -445,7 +445,14 @@ __global__ __launch_bounds__(256) void features_kernel(FeatureArgs a)
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= a.P) return;
     const int64_t y = p / a.W, x = p - y * a.W;
-    const float ir = (float)a.ir[y * a.pitch + x];
+    const uint8_t *img = a.ir;
+    int pitch = a.pitch;
+    if (a.job) {
+        const CensusJob *j = (const CensusJob *)a.job;
+        img = j->img;
+        pitch = j->pitch;
+    }
+    const float ir = (float)img[y * pitch + x];
     const float s1 = (float)a.s1[p];
     const uint32_t s2r = a.s2[p];
     const float s2 = s2r == 0xFFFFu ? a.smax : fminf((float)s2r, a.smax);
@@ -458,15 +465,30 @@ __global__ __launch_bounds__(256) void features_kernel(FeatureArgs a)
     *(uint4 *)(a.features + p * 8) = w;
 }
 
-// masked[p] = d2_sub + r where the logit is positive and the sum is positive, else 0
+// masked[p] = d2_sub + r where the logit is positive and the sum is positive, else 0;
+// optionally counts the pixels whose logit lies within (-tau, tau) (per block,
+// then one atomic add per block: an integer count, so the result is exact)
 __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a)
 {
+    __shared__ unsigned cnt[4];
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (p >= a.P) return;
-    const float d = __fadd_rn(a.d2_sub[p], a.out[p * 2]);
-    const bool ok = a.out[p * 2 + 1] > 0.0f && d > 0.0f;
-    a.masked[p] = ok ? d : 0.0f;
-    a.flags[p] = (uint8_t)(ok ? (SIMSENSE_FLAG_UNIQUE | SIMSENSE_FLAG_LR | SIMSENSE_FLAG_NONZERO) : 0u);
+    bool unsure = false;
+    if (p < a.P) {
+        const float z = a.out[p * 2 + 1];
+        const float d = __fadd_rn(a.d2_sub[p], a.out[p * 2]);
+        const bool ok = z > 0.0f && d > 0.0f;
+        a.masked[p] = ok ? d : 0.0f;
+        a.flags[p] = (uint8_t)(ok ? (SIMSENSE_FLAG_UNIQUE | SIMSENSE_FLAG_LR | SIMSENSE_FLAG_NONZERO) : 0u);
+        unsure = fabsf(z) < a.tau;
+    }
+    if (!a.uncertain) return;
+    const unsigned long long ball = __ballot(unsure);
+    if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = (unsigned)__popcll(ball);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned c = cnt[0] + cnt[1] + cnt[2] + cnt[3];
+        if (c) atomicAdd(a.uncertain, c);
+    }
 }
 
 hipError_t launch_features(const FeatureArgs &a, hipStream_t s)

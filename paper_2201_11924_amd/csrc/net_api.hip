@@ -32,24 +32,7 @@ int boff(int l) { return woff(l) + 9 * kLayers[l].cin * kLayers[l].cout; }
 using namespace ss;
 using namespace ss::net;
 
-struct simsense_net {
-    int64_t max_pixels;
-    int64_t step;
-    void *block;
-    float *params, *m, *v, *grad;
-    uint16_t *wf[4], *wb[4];
-    float *bias[4];
-    uint16_t *feat;        // [P][8] features of the learned depth path
-    uint16_t *act[3];      // [P][32] outputs of layers 1..3
-    float *out;            // [P][2]
-    uint16_t *dy4;         // [P][16]
-    uint16_t *g[2];        // [P][32] backward ping-pong
-    float *wpart, *bpart;  // weight / bias gradient partials
-    float *lpart, *scal, *loss;
-    float *t_res;          // targets of the learned depth path's own use (training helpers)
-    uint8_t *t_valid;
-    hipStream_t last_stream;
-};
+
 
 namespace {
 
@@ -102,7 +85,9 @@ RelayoutArgs relayout_args(simsense_net *n)
 #define NET_TRY(expr) \
     do { if ((expr) != hipSuccess) { (void)hipGetLastError(); return SIMSENSE_ERR_DEVICE; } } while (0)
 
-int enqueue_forward(simsense_net *n, const uint16_t *x0, int batch, int H, int W, hipStream_t s)
+}  // namespace
+
+int ss::net::enqueue_forward(simsense_net *n, const uint16_t *x0, int batch, int H, int W, hipStream_t s)
 {
     ConvArgs c{};
     c.batch = batch; c.H = H; c.W = W;
@@ -116,6 +101,8 @@ int enqueue_forward(simsense_net *n, const uint16_t *x0, int batch, int H, int W
     NET_TRY(launch_conv(c, 32, 16, EPI_LINEAR, s));
     return SIMSENSE_OK;
 }
+
+namespace {
 
 int check_shape(simsense_net *n, int batch, int H, int W)
 {

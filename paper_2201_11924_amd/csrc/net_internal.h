@@ -75,6 +75,7 @@ struct RelayoutArgs {
 struct FeatureArgs {
     const uint8_t *ir;  // left image
     int pitch, W;
+    const void *job;    // when set: a census job (device) whose image and pitch replace ir / pitch
     const uint16_t *s1, *s2;
     const uint8_t *dint;
     int max_disp;
@@ -88,6 +89,8 @@ struct CombineArgs {
     float *masked;
     uint8_t *flags;
     int64_t P;
+    unsigned *uncertain;  // nullable: pixels with |logit| < tau are counted here
+    float tau;
 };
 
 hipError_t launch_conv(const ConvArgs &a, int cinp, int coutp, int epi, hipStream_t s);
@@ -101,5 +104,33 @@ hipError_t launch_combine(const CombineArgs &a, hipStream_t s);
 hipError_t launch_targets(const float *d8_sub, const uint8_t *flags8, const float *d2_sub, float *t_res,
                           uint8_t *t_valid, int64_t n, hipStream_t s);
 
+}  // namespace net
+}  // namespace ss
+
+#include "../../include/simsense.h"
+
+struct simsense_net {
+    int64_t max_pixels;
+    int64_t step;
+    void *block;
+    float *params, *m, *v, *grad;
+    uint16_t *wf[4], *wb[4];
+    float *bias[4];
+    uint16_t *feat;        // [P][8] features of the learned depth path
+    uint16_t *act[3];      // [P][32] outputs of layers 1..3
+    float *out;            // [P][2]
+    uint16_t *dy4;         // [P][16]
+    uint16_t *g[2];        // [P][32] backward ping-pong
+    float *wpart, *bpart;  // weight / bias gradient partials
+    float *lpart, *scal, *loss;
+    float *t_res;          // targets of the learned depth path's own use (training helpers)
+    uint8_t *t_valid;
+    hipStream_t last_stream;
+};
+
+namespace ss {
+namespace net {
+// the net's four convolutions on `batch` images of height x width into n->out
+int enqueue_forward(simsense_net *n, const uint16_t *x0, int batch, int H, int W, hipStream_t s);
 }  // namespace net
 }  // namespace ss

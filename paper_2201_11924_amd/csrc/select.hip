@@ -125,15 +125,13 @@ __device__ __forceinline__ void sum_paths(const Words<DPL> (&v)[NDIR], uint32_t 
 }  // namespace
 
 template <int DPL, int NDIR, bool SMALL>
-__global__ __launch_bounds__(kSelBlock) void select_kernel(SelectArgs a)
+__device__ __forceinline__ void select_row(const SelectArgs &a, int y, uint32_t *smem)
 {
-    extern __shared__ uint32_t smem[];
     const int W = a.W, D = a.D, Dpad = a.Dpad;
     uint32_t *keyR = smem;                          // W
     float *dsub_row = (float *)(keyR + W);          // W
     uint8_t *dint_row = (uint8_t *)(dsub_row + W);  // W
     uint8_t *uniq_row = dint_row + W;               // W
-    const int y = blockIdx.x;
     const size_t row = (size_t)y * W;
     for (int x = threadIdx.x; x < W; x += kSelBlock) keyR[x] = 0xFFFFFFFFu;
     __syncthreads();
@@ -210,39 +208,69 @@ __global__ __launch_bounds__(kSelBlock) void select_kernel(SelectArgs a)
     }
 }
 
+template <int DPL, int NDIR, bool SMALL>
+__global__ __launch_bounds__(kSelBlock) void select_kernel(SelectArgs a)
+{
+    extern __shared__ uint32_t smem[];
+    select_row<DPL, NDIR, SMALL>(a, (int)blockIdx.x, smem);
+}
+
+// batch form: one block per (pair slot, row) item
+template <int DPL, int NDIR, bool SMALL>
+__global__ __launch_bounds__(kSelBlock) void select_batch_kernel(SelectBatch b)
+{
+    extern __shared__ uint32_t smem[];
+    const uint32_t it = b.items[blockIdx.x];
+    select_row<DPL, NDIR, SMALL>(b.slots[it >> 20], (int)(it & 0xFFFFFu), smem);
+}
+
 namespace {
 template <int DPL, int NDIR>
-void launch_sel3(const SelectArgs &a, hipStream_t s)
+void launch_sel3(const SelectArgs *a, const SelectBatch *b, bool small, hipStream_t s)
 {
-    dim3 grid(a.H), block(kSelBlock);
-    const size_t lds = (size_t)a.W * 10;
-    if (a.small_values)
-        hipLaunchKernelGGL((select_kernel<DPL, NDIR, true>), grid, block, lds, s, a);
-    else
-        hipLaunchKernelGGL((select_kernel<DPL, NDIR, false>), grid, block, lds, s, a);
+    dim3 block(kSelBlock);
+    if (a) {
+        const size_t lds = (size_t)a->W * 10;
+        if (small) hipLaunchKernelGGL((select_kernel<DPL, NDIR, true>), dim3(a->H), block, lds, s, *a);
+        else hipLaunchKernelGGL((select_kernel<DPL, NDIR, false>), dim3(a->H), block, lds, s, *a);
+    } else {
+        const size_t lds = (size_t)b->max_width * 10;
+        if (small) hipLaunchKernelGGL((select_batch_kernel<DPL, NDIR, true>), dim3(b->nitems), block, lds, s, *b);
+        else hipLaunchKernelGGL((select_batch_kernel<DPL, NDIR, false>), dim3(b->nitems), block, lds, s, *b);
+    }
 }
 template <int DPL>
-void launch_sel2(const SelectArgs &a, hipStream_t s)
+void launch_sel2(const SelectArgs *a, const SelectBatch *b, int ndirs, bool small, hipStream_t s)
 {
-    if (a.ndirs == 2) launch_sel3<DPL, 2>(a, s);
-    else if (a.ndirs == 4) launch_sel3<DPL, 4>(a, s);
-    else launch_sel3<DPL, 8>(a, s);
+    if (ndirs == 2) launch_sel3<DPL, 2>(a, b, small, s);
+    else if (ndirs == 4) launch_sel3<DPL, 4>(a, b, small, s);
+    else launch_sel3<DPL, 8>(a, b, small, s);
+}
+hipError_t launch_sel(const SelectArgs *a, const SelectBatch *b, int dpad, int ndirs, bool small, hipStream_t s)
+{
+    switch (dpad / kLanesPerLine) {
+    case 1: launch_sel2<1>(a, b, ndirs, small, s); break;
+    case 2: launch_sel2<2>(a, b, ndirs, small, s); break;
+    case 4: launch_sel2<4>(a, b, ndirs, small, s); break;
+    case 6: launch_sel2<6>(a, b, ndirs, small, s); break;
+    case 8: launch_sel2<8>(a, b, ndirs, small, s); break;
+    case 12: launch_sel2<12>(a, b, ndirs, small, s); break;
+    case 16: launch_sel2<16>(a, b, ndirs, small, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 }  // namespace
 
 hipError_t launch_select(const SelectArgs &a, hipStream_t s)
 {
-    switch (a.Dpad / kLanesPerLine) {
-    case 1: launch_sel2<1>(a, s); break;
-    case 2: launch_sel2<2>(a, s); break;
-    case 4: launch_sel2<4>(a, s); break;
-    case 6: launch_sel2<6>(a, s); break;
-    case 8: launch_sel2<8>(a, s); break;
-    case 12: launch_sel2<12>(a, s); break;
-    case 16: launch_sel2<16>(a, s); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    return launch_sel(&a, nullptr, a.Dpad, a.ndirs, a.small_values != 0, s);
+}
+
+hipError_t launch_select_batch(const SelectBatch &b, int dpad, int ndirs, bool small, hipStream_t s)
+{
+    if (b.nitems == 0) return hipSuccess;
+    return launch_sel(nullptr, &b, dpad, ndirs, small, s);
 }
 
 // ---------------------------------------------------------------- median + depth
@@ -267,9 +295,9 @@ __device__ __forceinline__ float median9(float p[9])
     return p[4];
 }
 
-__global__ __launch_bounds__(256) void post_kernel(PostArgs a)
+__device__ __forceinline__ void post_block(const PostArgs &a, int bx, int by)
 {
-    const int x = blockIdx.x * 64 + threadIdx.x % 64, y = blockIdx.y * 4 + threadIdx.x / 64;
+    const int x = bx * 64 + threadIdx.x % 64, y = by * 4 + threadIdx.x / 64;
     if (x >= a.W || y >= a.H) return;
     const size_t p = (size_t)y * a.W + x;
     float v = a.masked[p];
@@ -285,10 +313,28 @@ __global__ __launch_bounds__(256) void post_kernel(PostArgs a)
     if (a.depth) a.depth[p] = v > 0.0f ? __fdiv_rn(a.fb, v) : 0.0f;
 }
 
+__global__ __launch_bounds__(256) void post_kernel(PostArgs a) { post_block(a, blockIdx.x, blockIdx.y); }
+
+// batch form: one block per (pair slot, 64x4 tile) item; tile = by * ceil(W/64) + bx
+__global__ __launch_bounds__(256) void post_batch_kernel(PostBatch b)
+{
+    const uint32_t it = b.items[blockIdx.x];
+    const PostArgs &a = b.slots[it >> 20];
+    const int tile = (int)(it & 0xFFFFFu), tx = (a.W + 63) / 64;
+    post_block(a, tile % tx, tile / tx);
+}
+
 hipError_t launch_post(const PostArgs &a, hipStream_t s)
 {
     dim3 grid((a.W + 63) / 64, (a.H + 3) / 4), block(256);
     hipLaunchKernelGGL(post_kernel, grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_post_batch(const PostBatch &b, hipStream_t s)
+{
+    if (b.nitems == 0) return hipSuccess;
+    hipLaunchKernelGGL(post_batch_kernel, dim3(b.nitems), dim3(256), 0, s, b);
     return hipGetLastError();
 }
 

@@ -320,3 +320,101 @@ def learned_compute(ss: "SimSense", net: Net, left: torch.Tensor, right: torch.T
     _check(_lib.simsense_learned_compute(ss._h, net._h, _ptr(left), _ptr(right), W, ct.byref(o), _stream(stream)),
            "simsense_learned_compute")
     return out
+
+
+# ---------------------------------------------------------------- batches
+class Pair(ct.Structure):
+    _fields_ = [("left", _vp), ("right", _vp), ("pitch", _i32), ("depth", _vp), ("disp", _vp), ("flags", _vp)]
+
+
+class Tuning(ct.Structure):
+    _fields_ = [("struct_size", ct.c_uint32), ("horizontal_lanes", _i32), ("blocks_per_cu", _i32)]
+
+
+_lib.simsense_batch_create.argtypes = [ct.POINTER(Params), _i32, ct.POINTER(_vp)]
+_lib.simsense_batch_destroy.argtypes = [_vp]
+_lib.simsense_batch_scratch_bytes.argtypes = [_vp]
+_lib.simsense_batch_scratch_bytes.restype = _i64
+_lib.simsense_batch_compute.argtypes = [_vp, ct.POINTER(Pair), _vp]
+_lib.simsense_batch_set_tuning.argtypes = [_vp, ct.POINTER(Tuning)]
+_lib.simsense_batch_get_tuning.argtypes = [_vp, ct.POINTER(Tuning)]
+_lib.simsense_batch_learned_compute.argtypes = [_vp, _vp, ct.POINTER(Pair), ct.c_float, _vp, _vp]
+_lib.simsense_batch_autotune.argtypes = [_vp, ct.POINTER(Pair), _i32, ct.POINTER(Tuning), ct.POINTER(ct.c_float),
+                                         _i32, ct.POINTER(_i32), _vp]
+
+
+class Batch:
+    """Many pairs of uneven sizes, computed by one graph launch per call."""
+
+    def __init__(self, params_list):
+        self.params = [dict(p) for p in params_list]
+        arr = (Params * len(self.params))(*[Params.from_dict(p) for p in self.params])
+        h = ct.c_void_p()
+        _check(_lib.simsense_batch_create(arr, len(self.params), ct.byref(h)), "simsense_batch_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(_lib.simsense_batch_destroy(self._h), "simsense_batch_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def scratch_bytes(self) -> int:
+        return int(_lib.simsense_batch_scratch_bytes(self._h))
+
+    def outputs(self, device="cuda"):
+        outs = []
+        for p in self.params:
+            H, W = p["height"], p["width"]
+            outs.append(dict(depth=torch.empty((H, W), dtype=torch.float32, device=device),
+                             disp=torch.empty((H, W), dtype=torch.float32, device=device),
+                             flags=torch.empty((H, W), dtype=torch.uint8, device=device)))
+        return outs
+
+    def _pairs(self, lefts, rights, outs):
+        arr = (Pair * len(self.params))()
+        for i, (p, L, R, o) in enumerate(zip(self.params, lefts, rights, outs)):
+            _need(L, torch.uint8, (p["height"], p["width"]), f"left[{i}]")
+            _need(R, torch.uint8, (p["height"], p["width"]), f"right[{i}]")
+            arr[i] = Pair(L.data_ptr(), R.data_ptr(), p["width"], o["depth"].data_ptr(),
+                          o["disp"].data_ptr() if o.get("disp") is not None else None,
+                          o["flags"].data_ptr() if o.get("flags") is not None else None)
+        return arr
+
+    def compute(self, lefts, rights, outs, stream=None):
+        arr = self._pairs(lefts, rights, outs)
+        _check(_lib.simsense_batch_compute(self._h, arr, _stream(stream)), "simsense_batch_compute")
+
+    def learned_compute(self, net: "Net", lefts, rights, outs, tau: float, uncertain: torch.Tensor,
+                        stream=None):
+        """The learned form on every pair; `uncertain` (int32 GPU tensor, one per pair)
+        receives the count of pixels whose validity logit lies within (-tau, tau)."""
+        arr = self._pairs(lefts, rights, outs)
+        if uncertain.dtype != torch.int32 or uncertain.numel() != len(self.params) or not uncertain.is_cuda:
+            raise ValueError("uncertain: int32 GPU tensor with one entry per pair")
+        _check(_lib.simsense_batch_learned_compute(self._h, net._h, arr, float(tau), _ptr(uncertain),
+                                                   _stream(stream)), "simsense_batch_learned_compute")
+
+    def set_tuning(self, horizontal_lanes: int = 0, blocks_per_cu: int = 2):
+        t = Tuning(ct.sizeof(Tuning), horizontal_lanes, blocks_per_cu)
+        _check(_lib.simsense_batch_set_tuning(self._h, ct.byref(t)), "simsense_batch_set_tuning")
+
+    def get_tuning(self):
+        t = Tuning()
+        _check(_lib.simsense_batch_get_tuning(self._h, ct.byref(t)), "simsense_batch_get_tuning")
+        return dict(horizontal_lanes=t.horizontal_lanes, blocks_per_cu=t.blocks_per_cu)
+
+    def autotune(self, lefts, rights, outs, reps: int = 5, stream=None):
+        arr = self._pairs(lefts, rights, outs)
+        best = Tuning()
+        ms = (ct.c_float * 32)()
+        count = _i32()
+        _check(_lib.simsense_batch_autotune(self._h, arr, reps, ct.byref(best), ms, 32, ct.byref(count),
+                                            _stream(stream)), "simsense_batch_autotune")
+        return dict(horizontal_lanes=best.horizontal_lanes, blocks_per_cu=best.blocks_per_cu), list(ms)[:count.value]

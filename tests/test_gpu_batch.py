@@ -1,0 +1,139 @@
+"""Batches of uneven pairs: every pair of a graph-launched batch equals the
+single-pair result (which is itself parity-checked against the oracle), for
+every tuning candidate, and small pairs also match the oracle directly."""
+import numpy as np
+import pytest
+
+from synth import PairSpec, make_pair
+from synth.stereo import c1_like
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nat():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2201_11924_amd.native as n
+    return n
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+SHAPES = [(320, 240, 64), (97, 61, 37), (640, 480, 96), (160, 90, 128), (64, 48, 16), (848, 480, 128)]
+
+
+def make_batch_inputs(orc, shapes, seed0=100):
+    params, lefts, rights = [], [], []
+    for i, (W, H, D) in enumerate(shapes):
+        cfg = c1_like(W, H, D)
+        p = dict(cfg["params"])
+        if i % 3 == 1:
+            p["num_paths"] = 4
+        pr = make_pair(cfg["spec"], seed0 + i)
+        lefts.append(orc.ir_noise(pr.left, pr.gamma_l, pr.n_l))
+        rights.append(orc.ir_noise(pr.right, pr.gamma_r, pr.n_r))
+        params.append(p)
+    return params, lefts, rights
+
+
+def test_batch_matches_single_pairs_for_every_tuning(orc, nat):
+    import torch
+    params, lefts, rights = make_batch_inputs(orc, SHAPES)
+    L = [dev(a) for a in lefts]
+    R = [dev(a) for a in rights]
+    singles = []
+    for p, l, r in zip(params, L, R):
+        ss = nat.SimSense(p)
+        singles.append([t.cpu().numpy() for t in ss(l, r)])
+        ss.close()
+    b = nat.Batch(params)
+    outs = b.outputs()
+    for hl in (0, 16, 32, 64):
+        for bpc in (1, 3):
+            b.set_tuning(hl, bpc)
+            for _ in range(2):  # graph replays
+                for o in outs:
+                    for t in o.values():
+                        t.fill_(0)
+                b.compute(L, R, outs)
+                torch.cuda.synchronize()
+                for i, (o, s) in enumerate(zip(outs, singles)):
+                    assert np.array_equal(o["depth"].cpu().numpy(), s[0]), (hl, bpc, i)
+                    assert np.array_equal(o["disp"].cpu().numpy(), s[1]), (hl, bpc, i)
+                    assert np.array_equal(o["flags"].cpu().numpy(), s[2]), (hl, bpc, i)
+    b.close()
+
+
+def test_batch_small_pairs_match_oracle(orc, nat):
+    import torch
+    shapes = [(97, 61, 37), (64, 48, 16), (120, 40, 64)]
+    params, lefts, rights = make_batch_inputs(orc, shapes, seed0=7)
+    b = nat.Batch(params)
+    outs = b.outputs()
+    b.compute([dev(a) for a in lefts], [dev(a) for a in rights], outs)
+    torch.cuda.synchronize()
+    for p, l, r, o in zip(params, lefts, rights, outs):
+        ref = orc.sgm(p, l, r)
+        assert np.array_equal(o["flags"].cpu().numpy(), ref.flags)
+        assert np.max(np.abs(o["disp"].cpu().numpy() - ref.disp)) <= 1e-5
+    b.close()
+
+
+def test_autotune_reports_candidates_and_keeps_results(orc, nat):
+    import torch
+    params, lefts, rights = make_batch_inputs(orc, SHAPES[:4], seed0=40)
+    L = [dev(a) for a in lefts]
+    R = [dev(a) for a in rights]
+    b = nat.Batch(params)
+    outs = b.outputs()
+    b.compute(L, R, outs)
+    torch.cuda.synchronize()
+    before = [o["disp"].cpu().numpy() for o in outs]
+    best, ms = b.autotune(L, R, outs, reps=2)
+    assert len(ms) == 12 and all(m > 0 for m in ms)
+    assert best["horizontal_lanes"] in (16, 32, 64) and 1 <= best["blocks_per_cu"] <= 4
+    b.compute(L, R, outs)
+    torch.cuda.synchronize()
+    for o, x in zip(outs, before):
+        assert np.array_equal(o["disp"].cpu().numpy(), x)
+    b.close()
+
+
+def test_learned_batch_matches_single_pair_learned_path(orc, nat):
+    import torch
+    from oracle import net_oracle as no
+    W, H, D = 200, 120, 64
+    cfg = c1_like(W, H, D)
+    p2 = dict(cfg["params"], num_paths=2)
+    lefts, rights = [], []
+    for i in range(5):
+        pr = make_pair(cfg["spec"], 300 + i)
+        lefts.append(dev(orc.ir_noise(pr.left, pr.gamma_l, pr.n_l)))
+        rights.append(dev(orc.ir_noise(pr.right, pr.gamma_r, pr.n_r)))
+    rng = np.random.default_rng(9)
+    params = [(w, rng.uniform(-0.05, 0.05, b.shape)) for w, b in no.init_params(12)]
+    net = nat.Net(2 * W * H, seed=0)  # chunks of two pairs
+    net.set_state(no.flatten(params))
+    ss = nat.SimSense(p2)
+    singles = [nat.learned_compute(ss, net, l, r) for l, r in zip(lefts, rights)]
+    torch.cuda.synchronize()
+    singles = [{k: v.cpu().numpy() for k, v in o.items()} for o in singles]
+    b = nat.Batch([p2] * 5)
+    outs = b.outputs()
+    unc = torch.zeros(5, dtype=torch.int32, device="cuda")
+    for _ in range(2):
+        b.learned_compute(net, lefts, rights, outs, 0.5, unc)
+        torch.cuda.synchronize()
+        for o, s in zip(outs, singles):
+            for k in ("depth", "disp", "flags"):
+                assert np.array_equal(o[k].cpu().numpy(), s[k]), k
+        u = unc.cpu().numpy()
+        assert np.all(u >= 0) and np.all(u <= W * H)
+    b.close()
+    ss.close()
+    net.close()
