@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--fallback-frac", type=float, default=0.25,
                     help="fall back to 8-path for a pair when this share of its logits is within (-tau, tau)")
     ap.add_argument("--workers", type=int, default=12)
+    ap.add_argument("--calibration-copy-mb", type=int, default=0,
+                    help="after the timed steps, copy a buffer of this many MiB three times (a plain copy "
+                         "kernel of known size, the reference for hardware traffic counters)")
     ap.add_argument("--cpu-sample-rows", type=int, default=720,
                     help="rows of the 1280x720 pair the oracle times (full pair = 720)")
     return ap.parse_args()
@@ -278,6 +281,15 @@ def main():
         "roofline": roofline,
     }
     ss.close()
+    if args.calibration_copy_mb > 0:
+        n = args.calibration_copy_mb << 20
+        src = torch.empty(n, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = n
+        del src, dst
     if not args.no_batch:
         learned_and_batch_legs(nat, args, out, inputs)
         inputs = None

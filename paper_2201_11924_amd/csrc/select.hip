@@ -20,7 +20,9 @@ constexpr int kRowRor1 = 0x121, kRowRor2 = 0x122, kRowRor4 = 0x124, kRowRor8 = 0
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp(uint32_t v)
 {
-    return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xF, 0xF, false);
+    // a row rotation reads a valid lane for every lane: no old value, so the move
+    // folds into the consuming min / or as a DPP source
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, true);
 }
 
 __device__ __forceinline__ uint32_t row_min(uint32_t v)
@@ -128,12 +130,12 @@ template <int DPL, int NDIR, bool SMALL>
 __device__ __forceinline__ void select_row(const SelectArgs &a, int y, uint32_t *smem)
 {
     const int W = a.W, D = a.D, Dpad = a.Dpad;
-    uint32_t *keyR = smem;                          // W
-    float *dsub_row = (float *)(keyR + W);          // W
+    uint32_t *keyR = smem;                          // W + 1 (the last is a spare slot)
+    float *dsub_row = (float *)(keyR + W + 1);      // W
     uint8_t *dint_row = (uint8_t *)(dsub_row + W);  // W
     uint8_t *uniq_row = dint_row + W;               // W
     const size_t row = (size_t)y * W;
-    for (int x = threadIdx.x; x < W; x += kSelBlock) keyR[x] = 0xFFFFFFFFu;
+    for (int x = threadIdx.x; x <= W; x += kSelBlock) keyR[x] = 0xFFFFFFFFu;
     __syncthreads();
 
     const int lane = threadIdx.x % kLanesPerLine, group = threadIdx.x / kLanesPerLine;
@@ -171,7 +173,9 @@ __device__ __forceinline__ void select_row(const SelectArgs &a, int y, uint32_t 
             if (d < D && (d - dstar >= 2 || dstar - d >= 2)) s2 = min(s2, S[j]);
             if (d == dstar - 1) nb |= S[j] << 16;
             if (d == dstar + 1 && d < D) nb |= S[j];
-            if (d < D && x - d >= 0) atomicMin(&keyR[x - d], key[j]);
+            // no branch: lanes past the left edge hit the spare slot keyR[W], and padding
+            // disparities carry the key 0xFFFFFFFF, for which the minimum is a no-op
+            atomicMin(&keyR[x - d >= 0 ? x - d : W], key[j]);
         }
         s2 = row_min(s2);
         nb = row_or(nb);
@@ -230,11 +234,11 @@ void launch_sel3(const SelectArgs *a, const SelectBatch *b, bool small, hipStrea
 {
     dim3 block(kSelBlock);
     if (a) {
-        const size_t lds = (size_t)a->W * 10;
+        const size_t lds = (size_t)a->W * 10 + 4;
         if (small) hipLaunchKernelGGL((select_kernel<DPL, NDIR, true>), dim3(a->H), block, lds, s, *a);
         else hipLaunchKernelGGL((select_kernel<DPL, NDIR, false>), dim3(a->H), block, lds, s, *a);
     } else {
-        const size_t lds = (size_t)b->max_width * 10;
+        const size_t lds = (size_t)b->max_width * 10 + 4;
         if (small) hipLaunchKernelGGL((select_batch_kernel<DPL, NDIR, true>), dim3(b->nitems), block, lds, s, *b);
         else hipLaunchKernelGGL((select_batch_kernel<DPL, NDIR, false>), dim3(b->nitems), block, lds, s, *b);
     }
