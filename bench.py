@@ -179,7 +179,7 @@ def learned_and_batch_legs(nat, args, out, inputs):
         "learned_pairs_s_with_fallback_cost": round(npairs / (ms2 / 1000.0 + fall.sum() / pairs8), 2)}
     b2.close()
     net.close()
-    del Ls, Rs, outs2, outs8, raws
+    del Ls, Rs, outs2, outs8
     torch.cuda.empty_cache()
 
     # 64 pairs of uneven sizes and disparity ranges in one graph launch, autotuned
