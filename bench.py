@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--calibration-copy-mb", type=int, default=0,
                     help="after the timed steps, copy a buffer of this many MiB three times (a plain copy "
                          "kernel of known size, the reference for hardware traffic counters)")
+    ap.add_argument("--no-paper-shape", action="store_true",
+                    help="skip the leg at the paper's own timing shape (960x540, 4 paths, D in 64..256)")
     ap.add_argument("--cpu-sample-rows", type=int, default=720,
                     help="rows of the 1280x720 pair the oracle times (full pair = 720)")
     return ap.parse_args()
@@ -206,6 +208,45 @@ def learned_and_batch_legs(nat, args, out, inputs):
     out["learned_and_batches"] = res
 
 
+# Sec. VI-D, Table II: SGM frames/s of the paper's implementation at 960x540 with
+# 4 paths on an NVIDIA RTX 4090 (another GPU; quoted as context only)
+PAPER_TABLE2_SGM_FPS = {64: 414.51, 96: 326.79, 128: 281.26, 256: 147.13}
+
+
+def paper_shape_leg(nat, reps=100):
+    """Plain SGM at the shape the paper times: 960x540, 4 paths, D = 64/96/128/256."""
+    import torch
+    from synth import make_pair, pair_seed
+    from synth.stereo import c1_like
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    res = {}
+    for i, D in enumerate(sorted(PAPER_TABLE2_SGM_FPS)):
+        cfg = c1_like(960, 540, D)
+        params = dict(cfg["params"], num_paths=4)
+        pr = make_pair(cfg["spec"], pair_seed(5, i))
+        L = nat.ir_noise(t(pr.left), t(pr.gamma_l), t(pr.n_l))
+        R = nat.ir_noise(t(pr.right), t(pr.gamma_r), t(pr.n_r))
+        ss = nat.SimSense(params)
+        depth = torch.empty((540, 960), dtype=torch.float32, device="cuda")
+        for _ in range(10):
+            ss.compute(L, R, depth)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            ss.compute(L, R, depth)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        ss.close()
+        fps = 1000.0 / ms
+        res[f"D{D}"] = {"fps": round(fps, 1), "ms": round(ms, 4),
+                        "mpix_disp_per_s": round(960 * 540 * D * fps / 1e6, 1),
+                        "paper_fps_rtx4090": PAPER_TABLE2_SGM_FPS[D]}
+    return {"shape": "960x540, 4 paths, census 7x9 CS, depth output at 960x540 (the paper's 1920x1080 "
+                     "registration is not part of this path)", "by_max_disp": res}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -290,6 +331,8 @@ def main():
         torch.cuda.synchronize()
         out["calibration_copy_bytes"] = n
         del src, dst
+    if not args.no_paper_shape:
+        out["paper_shape_4path_960x540"] = paper_shape_leg(nat)
     if not args.no_batch:
         learned_and_batch_legs(nat, args, out, inputs)
         inputs = None

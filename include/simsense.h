@@ -183,6 +183,20 @@ int simsense_net_get_grads(simsense_net *net, float *grads, int64_t count);
 int simsense_net_forward(simsense_net *net, const uint16_t *features, int32_t batch, int32_t height,
                          int32_t width, float *out, void *stream);
 
+/* Fused inference for the learned depth path: the four convolutions and the
+ * combination with the 2-path disparity in one kernel, with no activation
+ * written to memory; it allocates nothing and needs no max_pixels room.
+ * `features`: bf16 [batch][height][width][8] (device).  `out` (device,
+ * nullable): fp32 [batch][height][width][2], equal bit for bit to
+ * simsense_net_forward's.  `d2_sub`, `masked`, `flags` (device, all NULL or all
+ * set, [batch][height][width]): masked = d2_sub + residual where the logit and
+ * that sum are both positive, else 0; flags = 7 (unique, LR, nonzero) there,
+ * else 0.  `uncertain` (device, nullable, [batch]): the number of pixels whose
+ * logit lies within (-tau, tau) is ADDED to each image's counter. */
+int simsense_net_infer(simsense_net *net, const uint16_t *features, int32_t batch, int32_t height, int32_t width,
+                       const float *d2_sub, float *out, float *masked, uint8_t *flags, float tau,
+                       unsigned *uncertain, void *stream);
+
 /* One Adam step on a batch.  `target_residual` fp32 and `target_valid` uint8 (0/1)
  * are [batch][height][width] (device).  `loss` (device, nullable) receives
  * {total, l1, bce} of the forward pass before the update. */
@@ -262,6 +276,24 @@ int simsense_batch_get_tuning(const simsense_batch *b, simsense_batch_tuning *t)
 int simsense_batch_autotune(simsense_batch *b, const simsense_pair *pairs, int32_t reps,
                             simsense_batch_tuning *best, float *ms, int32_t max_candidates, int32_t *count,
                             void *stream);
+
+/* Launch shape of one handle's aggregation pass (the results do not depend on
+ * it).  Same struct as the batch tuning, with blocks_per_cu 0 meaning one
+ * block per line block of work (a grid of all of them, in direction order) and
+ * 1..8 a persistent grid of that many blocks per compute unit that takes line
+ * blocks longest first.  Default: horizontal_lanes 0, blocks_per_cu 3.
+ * Synchronous (uploads the work list); returns SIMSENSE_ERR_INVALID_ARGUMENT
+ * for values outside those ranges or a lane count that does not divide the
+ * padded disparity count. */
+int simsense_set_tuning(simsense_handle *h, const simsense_batch_tuning *t);
+int simsense_get_tuning(const simsense_handle *h, simsense_batch_tuning *t);
+/* Times every candidate (the valid horizontal_lanes of {16, 32, 64} x
+ * blocks_per_cu in {0, 1, 2, 3, 4}) over `reps` matching passes (census ..
+ * selection) of the given pair, writes the mean milliseconds of candidate i to
+ * ms[i] (host, up to max_candidates) and their number to *count, keeps the
+ * fastest and returns it in *best.  Synchronous. */
+int simsense_autotune(simsense_handle *h, const uint8_t *left, const uint8_t *right, int32_t pitch, int32_t reps,
+                      simsense_batch_tuning *best, float *ms, int32_t max_candidates, int32_t *count, void *stream);
 
 /* Human-readable name of a status code (static storage). */
 const char *simsense_strerror(int status);

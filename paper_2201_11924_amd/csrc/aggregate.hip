@@ -66,6 +66,20 @@ int aggregate_block_clocks(int dx, int dy, int blk, int W, int H, int hl)
     return c;
 }
 
+namespace {
+__global__ void zero_counters_kernel(unsigned *c, int n)
+{
+    if ((int)threadIdx.x < n) c[threadIdx.x] = 0u;
+}
+}  // namespace
+
+hipError_t launch_zero_counters(unsigned *c, int n, hipStream_t s)
+{
+    if (n < 1 || n > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(64), 0, s, c, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_aggregate(const AggregateArgs &a, bool wide, int hl, hipStream_t s)
 {
     if (a.block_begin[a.ndirs] == 0) return hipSuccess;

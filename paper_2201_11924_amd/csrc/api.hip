@@ -1,7 +1,10 @@
 // C ABI of the depth library: parameter validation, the handle and its device
 // scratch, and the order in which the passes are enqueued.
+#include <algorithm>
 #include <new>
 #include <string.h>
+#include <utility>
+#include <vector>
 
 #include "internal.h"
 #include "net_internal.h"
@@ -132,6 +135,53 @@ void profile_mark(simsense_handle *h, int pass, bool end, hipStream_t s)
 #define SS_TRY(expr) \
     do { if ((expr) != hipSuccess) { (void)hipGetLastError(); return SIMSENSE_ERR_DEVICE; } } while (0)
 
+// The handle's aggregation arguments (every pointer is handle scratch, so they
+// are fixed for its life).
+static AggregateArgs handle_aggregate_args(const simsense_handle *h)
+{
+    const simsense_params &p = h->p;
+    AggregateArgs ag{};
+    ag.census_l = h->census_l;
+    ag.census_r = h->census_r;
+    ag.W = p.width; ag.H = p.height; ag.D = p.max_disp; ag.Dpad = h->Dpad; ag.bits = h->bits;
+    ag.p1 = p.p1; ag.p2 = p.p2;
+    ag.ndirs = h->ndirs;
+    ag.block_begin[0] = 0;
+    for (int r = 0; r < h->ndirs; ++r) {
+        ag.dx[r] = kPathDx[r];
+        ag.dy[r] = kPathDy[r];
+        ag.out[r] = h->paths[r];
+        ag.block_begin[r + 1] = ag.block_begin[r] + aggregate_blocks(kPathDx[r], kPathDy[r], p.width, p.height, h->hlanes);
+    }
+    return ag;
+}
+
+// Applies a tuning: lane count, and for the persistent form the work list of
+// line blocks sorted longest first (stable, so equal lengths keep direction order).
+static int apply_tuning(simsense_handle *h, const simsense_batch_tuning &t)
+{
+    const int hl = t.horizontal_lanes == 0 ? horizontal_lanes(h->Dpad) : t.horizontal_lanes;
+    if (!horizontal_lanes_valid(h->Dpad, hl)) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    h->hlanes = hl;
+    h->tuning = t;
+    const AggregateArgs ag = handle_aggregate_args(h);
+    std::vector<std::pair<int, uint32_t>> lst;
+    for (int r = 0; r < h->ndirs; ++r)
+        for (int k = 0; k < ag.block_begin[r + 1] - ag.block_begin[r]; ++k)
+            lst.push_back({aggregate_block_clocks(kPathDx[r], kPathDy[r], k, h->p.width, h->p.height, hl),
+                           (uint32_t)(ag.block_begin[r] + k)});
+    std::stable_sort(lst.begin(), lst.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
+    std::vector<uint32_t> items(lst.size());
+    for (size_t i = 0; i < lst.size(); ++i) items[i] = lst[i].second;  // pair slot 0
+    if (h->d_items) (void)hipFree(h->d_items);
+    h->d_items = nullptr;
+    h->nitems = (int)items.size();
+    SS_TRY(hipMalloc(&h->d_items, std::max<size_t>(items.size(), 1) * sizeof(uint32_t)));
+    if (!items.empty()) SS_TRY(hipMemcpy(h->d_items, items.data(), items.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    SS_TRY(hipMemcpy(h->d_args, &ag, sizeof(ag), hipMemcpyHostToDevice));
+    return SIMSENSE_OK;
+}
+
 int enqueue_match(simsense_handle *h, const uint8_t *left, const uint8_t *right, int pitch, hipStream_t s)
 {
     const simsense_params &p = h->p;
@@ -142,21 +192,23 @@ int enqueue_match(simsense_handle *h, const uint8_t *left, const uint8_t *right,
     SS_TRY(launch_census(right, pitch, W, H, p.census_w, p.census_h, p.census_mode, h->census_r, h->wide, s));
     profile_mark(h, SIMSENSE_PASS_CENSUS, true, s);
 
-    AggregateArgs ag{};
-    ag.census_l = h->census_l;
-    ag.census_r = h->census_r;
-    ag.W = W; ag.H = H; ag.D = D; ag.Dpad = h->Dpad; ag.bits = h->bits; ag.p1 = p.p1; ag.p2 = p.p2;
-    ag.ndirs = h->ndirs;
-    ag.block_begin[0] = 0;
-    for (int r = 0; r < h->ndirs; ++r) {
-        ag.dx[r] = kPathDx[r];
-        ag.dy[r] = kPathDy[r];
-        ag.out[r] = h->paths[r];
-        ag.block_begin[r + 1] = ag.block_begin[r] + aggregate_blocks(kPathDx[r], kPathDy[r], W, H, h->hlanes);
+    if (h->tuning.blocks_per_cu > 0) {
+        AggregateQueue q{};
+        q.slots = h->d_args;
+        q.items = h->d_items;
+        q.nitems = h->nitems;
+        q.counter = h->d_counter;
+        const int grid = std::min(h->nitems, h->tuning.blocks_per_cu * h->num_cus);
+        SS_TRY(launch_zero_counters(h->d_counter, 1, s));
+        profile_mark(h, SIMSENSE_PASS_AGGREGATE, false, s);
+        SS_TRY(launch_aggregate_queue(q, h->Dpad, h->wide, h->hlanes, grid, s));
+        profile_mark(h, SIMSENSE_PASS_AGGREGATE, true, s);
+    } else {
+        const AggregateArgs ag = handle_aggregate_args(h);
+        profile_mark(h, SIMSENSE_PASS_AGGREGATE, false, s);
+        SS_TRY(launch_aggregate(ag, h->wide, h->hlanes, s));
+        profile_mark(h, SIMSENSE_PASS_AGGREGATE, true, s);
     }
-    profile_mark(h, SIMSENSE_PASS_AGGREGATE, false, s);
-    SS_TRY(launch_aggregate(ag, h->wide, h->hlanes, s));
-    profile_mark(h, SIMSENSE_PASS_AGGREGATE, true, s);
 
     SelectArgs sa{};
     for (int r = 0; r < h->ndirs; ++r) sa.paths[r] = h->paths[r];
@@ -227,8 +279,15 @@ int simsense_create(const simsense_params *params, simsense_handle **out)
     h->Dpad = padded_disp(params->max_disp);
     h->hlanes = horizontal_lanes(h->Dpad);
     h->ndirs = params->num_paths;
-    if (hipMalloc(&h->block, l.total) != hipSuccess) {
+    if (hipDeviceGetAttribute(&h->num_cus, hipDeviceAttributeMultiprocessorCount, 0) != hipSuccess) {
         (void)hipGetLastError();
+        h->num_cus = 256;
+    }
+    if (hipMalloc(&h->block, l.total) != hipSuccess || hipMalloc(&h->d_counter, 256) != hipSuccess ||
+        hipMalloc(&h->d_args, sizeof(AggregateArgs)) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(h->block);
+        (void)hipFree(h->d_counter);
         delete h;
         return SIMSENSE_ERR_OUT_OF_MEMORY;
     }
@@ -247,6 +306,15 @@ int simsense_create(const simsense_params *params, simsense_handle **out)
     h->profiling = false;
     h->prof_events = nullptr;
     h->prof_used = h->prof_calls = 0;
+    simsense_batch_tuning t{};
+    t.struct_size = sizeof(t);
+    t.horizontal_lanes = 0;
+    t.blocks_per_cu = 3;
+    rc = apply_tuning(h, t);
+    if (rc != SIMSENSE_OK) {
+        (void)simsense_destroy(h);
+        return rc;
+    }
     *out = h;
     return SIMSENSE_OK;
 }
@@ -257,6 +325,9 @@ int simsense_destroy(simsense_handle *h)
     int rc = SIMSENSE_OK;
     if (hipStreamSynchronize(h->last_stream) != hipSuccess) rc = SIMSENSE_ERR_DEVICE;
     if (hipFree(h->block) != hipSuccess) rc = SIMSENSE_ERR_DEVICE;
+    if (hipFree(h->d_items) != hipSuccess) rc = SIMSENSE_ERR_DEVICE;
+    if (hipFree(h->d_counter) != hipSuccess) rc = SIMSENSE_ERR_DEVICE;
+    if (hipFree(h->d_args) != hipSuccess) rc = SIMSENSE_ERR_DEVICE;
     prof_free(h);
     delete h;
     return rc;
@@ -381,6 +452,79 @@ int simsense_census(const simsense_params *params, const uint8_t *img, int32_t p
         return SIMSENSE_ERR_DEVICE;
     }
     return SIMSENSE_OK;
+}
+
+int simsense_set_tuning(simsense_handle *h, const simsense_batch_tuning *t)
+{
+    if (!h || !t) return SIMSENSE_ERR_NULL_POINTER;
+    if (t->struct_size != sizeof(simsense_batch_tuning)) return SIMSENSE_ERR_ABI;
+    if (t->horizontal_lanes != 0 && !horizontal_lanes_valid(h->Dpad, t->horizontal_lanes))
+        return SIMSENSE_ERR_INVALID_ARGUMENT;
+    if (t->blocks_per_cu < 0 || t->blocks_per_cu > 8) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    if (h->last_stream && hipStreamSynchronize(h->last_stream) != hipSuccess) return SIMSENSE_ERR_DEVICE;
+    return apply_tuning(h, *t);
+}
+
+int simsense_get_tuning(const simsense_handle *h, simsense_batch_tuning *t)
+{
+    if (!h || !t) return SIMSENSE_ERR_NULL_POINTER;
+    *t = h->tuning;
+    return SIMSENSE_OK;
+}
+
+int simsense_autotune(simsense_handle *h, const uint8_t *left, const uint8_t *right, int32_t pitch, int32_t reps,
+                      simsense_batch_tuning *best, float *ms, int32_t max_candidates, int32_t *count, void *stream)
+{
+    if (!h || !left || !right || !best) return SIMSENSE_ERR_NULL_POINTER;
+    if (reps < 1 || pitch < h->p.width) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    hipStream_t st = (hipStream_t)stream;
+    static const int lanes[3] = {16, 32, 64};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return SIMSENSE_ERR_DEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return SIMSENSE_ERR_DEVICE;
+    }
+    const bool was_profiling = h->profiling;
+    h->profiling = false;
+    float best_ms = 1e30f;
+    simsense_batch_tuning best_t = h->tuning;
+    int c = 0, rc = SIMSENSE_OK;
+    for (int li = 0; li < 3 && rc == SIMSENSE_OK; ++li) {
+        if (!horizontal_lanes_valid(h->Dpad, lanes[li])) continue;
+        for (int bpc = 0; bpc <= 4 && rc == SIMSENSE_OK; ++bpc) {
+            simsense_batch_tuning t{};
+            t.struct_size = sizeof(t);
+            t.horizontal_lanes = lanes[li];
+            t.blocks_per_cu = bpc;
+            rc = simsense_set_tuning(h, &t);
+            if (rc == SIMSENSE_OK) rc = enqueue_match(h, left, right, pitch, st);  // warm-up
+            if (rc != SIMSENSE_OK) break;
+            if (hipEventRecord(e0, st) != hipSuccess) { rc = SIMSENSE_ERR_DEVICE; break; }
+            for (int r = 0; r < reps && rc == SIMSENSE_OK; ++r) rc = enqueue_match(h, left, right, pitch, st);
+            if (rc != SIMSENSE_OK) break;
+            float m = 0.0f;
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&m, e0, e1) != hipSuccess) {
+                rc = SIMSENSE_ERR_DEVICE;
+                break;
+            }
+            m /= (float)reps;
+            if (ms && c < max_candidates) ms[c] = m;
+            ++c;
+            if (m < best_ms) {
+                best_ms = m;
+                best_t = t;
+            }
+        }
+    }
+    h->profiling = was_profiling;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (count) *count = c;
+    if (rc != SIMSENSE_OK) return rc;
+    *best = best_t;
+    return simsense_set_tuning(h, &best_t);
 }
 
 }  // extern "C"

@@ -31,11 +31,6 @@ struct Slot {
 
 size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-__global__ void zero_counters(unsigned *c, int n)
-{
-    if ((int)threadIdx.x < n) c[threadIdx.x] = 0u;
-}
-
 }  // namespace
 
 struct simsense_batch {
@@ -213,8 +208,7 @@ __global__ void zero_words(unsigned *c, int n)
 int enqueue_match_batch(simsense_batch *b, hipStream_t s)
 {
     const int ngroups = (int)b->agg_groups.size();
-    hipLaunchKernelGGL(zero_counters, dim3(1), dim3(64), 0, s, b->d_counters, ngroups);
-    B_TRY(hipGetLastError());
+    if (ngroups > 0) B_TRY(launch_zero_counters(b->d_counters, ngroups, s));
     CensusBatch cb{};
     cb.jobs = b->d_cjobs;
     cb.items = b->d_items + b->census_item_off;
@@ -287,19 +281,31 @@ int enqueue_learned_batch(simsense_batch *b, simsense_net *net, float tau, unsig
             fa.P = P;
             B_TRY(net::launch_features(fa, s));
         }
-        rc = net::enqueue_forward(net, net->feat, cn, H, W, s);
-        if (rc != SIMSENSE_OK) return rc;
-        for (int k = 0; k < cn; ++k) {
+        // the fused net + combination, one launch for the chunk when its slots'
+        // buffers lie at equal distances (equal-sized slots do), else per slot
+        auto gap = [&](size_t Slot::*off, int k) {
+            return (int64_t)(b->slots[c0 + k].*off) - (int64_t)(b->slots[c0 + k - 1].*off);
+        };
+        bool uniform = true;
+        for (int k = 2; k < cn && uniform; ++k)
+            uniform = gap(&Slot::off_dsub, k) == gap(&Slot::off_dsub, 1) &&
+                      gap(&Slot::off_masked, k) == gap(&Slot::off_masked, 1) &&
+                      gap(&Slot::off_flags, k) == gap(&Slot::off_flags, 1);
+        const int per = uniform ? cn : 1;
+        for (int k = 0; k < cn; k += per) {
             const Slot &sl = b->slots[c0 + k];
-            net::CombineArgs ca{};
-            ca.d2_sub = (const float *)(b->scratch + sl.off_dsub);
-            ca.out = net->out + (size_t)k * P * 2;
-            ca.masked = (float *)(b->scratch + sl.off_masked);
-            ca.flags = b->scratch + sl.off_flags;
-            ca.P = P;
-            ca.uncertain = uncertain + c0 + k;
-            ca.tau = tau;
-            B_TRY(net::launch_combine(ca, s));
+            net::InferArgs ia = net::infer_args(net, net->feat + (size_t)k * P * 8, per, H, W);
+            ia.d2_sub = (const float *)(b->scratch + sl.off_dsub);
+            ia.masked = (float *)(b->scratch + sl.off_masked);
+            ia.flags = b->scratch + sl.off_flags;
+            if (per > 1) {
+                ia.d2_stride = gap(&Slot::off_dsub, 1) / 4;
+                ia.masked_stride = gap(&Slot::off_masked, 1) / 4;
+                ia.flags_stride = gap(&Slot::off_flags, 1);
+            }
+            ia.uncertain = uncertain + c0 + k;
+            ia.tau = tau;
+            B_TRY(net::launch_infer(ia, s));
         }
     }
     return enqueue_post_batch(b, s);

@@ -79,6 +79,8 @@ struct AggregateQueue {
     unsigned *counter;           // zero before the launch
 };
 hipError_t launch_aggregate(const AggregateArgs &a, bool wide, int hl, hipStream_t s);
+// zeroes n <= 64 queue counters (a kernel, so that it may sit in a captured graph)
+hipError_t launch_zero_counters(unsigned *c, int n, hipStream_t s);
 hipError_t launch_aggregate_queue(const AggregateQueue &q, int dpad, bool wide, int hl, int grid, hipStream_t s);
 hipError_t launch_select(const SelectArgs &a, hipStream_t s);
 hipError_t launch_post(const PostArgs &a, hipStream_t s);
@@ -134,6 +136,13 @@ struct simsense_handle {  // opaque to callers
     int bits, Dpad, ndirs;
     int hlanes;  // lanes per horizontal scanline
     bool wide;
+    // launch shape of the aggregation; for the persistent form, the work list
+    // (line blocks longest first), its counter and the argument block on the device
+    simsense_batch_tuning tuning;
+    int num_cus, nitems;
+    uint32_t *d_items;
+    unsigned *d_counter;
+    ss::AggregateArgs *d_args;
     void *block;
     void *census_l, *census_r;
     uint8_t *paths[8];

@@ -102,6 +102,20 @@ int ss::net::enqueue_forward(simsense_net *n, const uint16_t *x0, int batch, int
     return SIMSENSE_OK;
 }
 
+InferArgs ss::net::infer_args(const simsense_net *n, const uint16_t *feat, int batch, int H, int W)
+{
+    InferArgs a{};
+    a.feat = feat;
+    for (int l = 0; l < 4; ++l) {
+        a.w[l] = n->wf[l];
+        a.b[l] = n->bias[l];
+    }
+    const int64_t P = (int64_t)H * W;
+    a.d2_stride = a.masked_stride = a.flags_stride = P;
+    a.batch = batch; a.H = H; a.W = W;
+    return a;
+}
+
 namespace {
 
 int check_shape(simsense_net *n, int batch, int H, int W)
@@ -331,6 +345,24 @@ int simsense_net_targets(const float *d8_sub, const uint8_t *flags8, const float
     return SIMSENSE_OK;
 }
 
+int simsense_net_infer(simsense_net *n, const uint16_t *features, int32_t batch, int32_t height, int32_t width,
+                       const float *d2_sub, float *out, float *masked, uint8_t *flags, float tau,
+                       unsigned *uncertain, void *stream)
+{
+    if (!n || !features) return SIMSENSE_ERR_NULL_POINTER;
+    if (batch < 1 || height < 1 || width < 1) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    const int set = (d2_sub != nullptr) + (masked != nullptr) + (flags != nullptr);
+    if (set != 0 && set != 3) return SIMSENSE_ERR_NULL_POINTER;
+    if ((int64_t)batch * height * width > ((int64_t)1 << 40)) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    hipStream_t s = (hipStream_t)stream;
+    n->last_stream = s;
+    InferArgs a = infer_args(n, features, batch, height, width);
+    a.d2_sub = d2_sub; a.masked = masked; a.flags = flags; a.out = out;
+    a.uncertain = uncertain; a.tau = tau;
+    NET_TRY(launch_infer(a, s));
+    return SIMSENSE_OK;
+}
+
 int simsense_learned_compute(simsense_handle *h, simsense_net *n, const uint8_t *left, const uint8_t *right,
                              int32_t pitch, const simsense_outputs *o, void *stream)
 {
@@ -351,11 +383,9 @@ int simsense_learned_compute(simsense_handle *h, simsense_net *n, const uint8_t 
     fa.max_disp = p.max_disp; fa.smax = (float)(h->ndirs * (h->bits + p.p2));
     fa.features = n->feat; fa.P = P;
     NET_TRY(launch_features(fa, s));
-    rc = enqueue_forward(n, n->feat, 1, p.height, p.width, s);
-    if (rc != SIMSENSE_OK) return rc;
-    CombineArgs ca{};
-    ca.d2_sub = h->disp_sub; ca.out = n->out; ca.masked = h->masked; ca.flags = h->flags_pre; ca.P = P;
-    NET_TRY(launch_combine(ca, s));
+    InferArgs ia = infer_args(n, n->feat, 1, p.height, p.width);
+    ia.d2_sub = h->disp_sub; ia.masked = h->masked; ia.flags = h->flags_pre;
+    NET_TRY(launch_infer(ia, s));
     rc = enqueue_post(h, h->masked, h->flags_pre, o, s);
     if (rc != SIMSENSE_OK) return rc;
     profile_end_call(h);

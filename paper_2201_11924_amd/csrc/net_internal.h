@@ -93,7 +93,29 @@ struct CombineArgs {
     float tau;
 };
 
+// Fused inference (all four layers, then the combination with the 2-path
+// disparity) on `batch` images whose per-pixel outputs lie `*_stride` elements
+// apart; masked / flags / d2_sub / out / uncertain may each be null.
+struct InferArgs {
+    const uint16_t *feat;  // bf16 [batch][H][W][8]
+    const uint16_t *w[4];  // forward layouts, bf16 [COUTP][kpad(CINP)]
+    const float *b[4];     // fp32 [COUTP]
+    const float *d2_sub;
+    int64_t d2_stride;
+    float *masked;
+    int64_t masked_stride;
+    uint8_t *flags;
+    int64_t flags_stride;
+    unsigned *uncertain;   // one counter per image: pixels with |logit| < tau
+    float tau;
+    float *out;            // fp32 [batch][H][W][2] residual and logit, or null
+    int batch, H, W;
+    int seg_rows;          // rows per block (0 = default); segs / strips are set by the launcher
+    int segs, strips;
+};
+
 hipError_t launch_conv(const ConvArgs &a, int cinp, int coutp, int epi, hipStream_t s);
+hipError_t launch_infer(InferArgs a, hipStream_t s);
 hipError_t launch_wgrad(const WgradArgs &a, int cinp, int coutp, int nblocks, int nbblocks, hipStream_t s);
 hipError_t launch_wgrad_reduce(const WgradReduceArgs &a, hipStream_t s);
 hipError_t launch_loss(const LossArgs &a, int nblocks, hipStream_t s);
@@ -132,5 +154,8 @@ namespace ss {
 namespace net {
 // the net's four convolutions on `batch` images of height x width into n->out
 int enqueue_forward(simsense_net *n, const uint16_t *x0, int batch, int H, int W, hipStream_t s);
+// fused-inference arguments for the net's current weights (outputs unset,
+// per-image strides of one image)
+InferArgs infer_args(const simsense_net *n, const uint16_t *feat, int batch, int H, int W);
 }  // namespace net
 }  // namespace ss

@@ -34,15 +34,6 @@ __device__ __forceinline__ uint32_t row_min(uint32_t v)
     return v;
 }
 
-__device__ __forceinline__ uint32_t row_or(uint32_t v)
-{
-    v |= dpp<kRowRor8>(v);
-    v |= dpp<kRowRor4>(v);
-    v |= dpp<kRowRor2>(v);
-    v |= dpp<kRowRor1>(v);
-    return v;
-}
-
 constexpr int kSelBlock = 512;                            // one image row per block
 constexpr int kSelGroups = kSelBlock / kLanesPerLine;     // pixels in flight per row
 
@@ -126,62 +117,151 @@ __device__ __forceinline__ void sum_paths(const Words<DPL> (&v)[NDIR], uint32_t 
 
 }  // namespace
 
+// A group's row of S(d) in LDS, as 16-bit values in disparity order: stores of
+// the lane's dpl values (pairs packed into words) and the matching loads.
+template <int DPL>
+__device__ __forceinline__ void store_row(uint16_t *dst, const uint32_t (&S)[DPL])
+{
+    if constexpr (DPL == 1) {
+        *dst = (uint16_t)S[0];
+    } else {
+        constexpr int NW = DPL / 2;
+        uint32_t w[NW];
+#pragma unroll
+        for (int i = 0; i < NW; ++i) w[i] = S[2 * i] | (S[2 * i + 1] << 16);
+        if constexpr (NW % 4 == 0) {
+#pragma unroll
+            for (int i = 0; i < NW; i += 4) *(uint4 *)(dst + 2 * i) = make_uint4(w[i], w[i + 1], w[i + 2], w[i + 3]);
+        } else if constexpr (NW % 2 == 0) {
+#pragma unroll
+            for (int i = 0; i < NW; i += 2) *(uint2 *)(dst + 2 * i) = make_uint2(w[i], w[i + 1]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < NW; ++i) *(uint32_t *)(dst + 2 * i) = w[i];
+        }
+    }
+}
+
+typedef unsigned short ushort2_t __attribute__((ext_vector_type(2)));
+
+// minimum of the lane's dpl 16-bit values of the row (packed 16-bit minima)
+template <int DPL>
+__device__ __forceinline__ uint32_t row_slice_min(const uint16_t *src)
+{
+    if constexpr (DPL == 1) {
+        return *src;
+    } else {
+        constexpr int NW = DPL / 2;
+        uint32_t w[NW];
+        if constexpr (NW % 4 == 0) {
+#pragma unroll
+            for (int i = 0; i < NW; i += 4) {
+                const uint4 v = *(const uint4 *)(src + 2 * i);
+                w[i] = v.x; w[i + 1] = v.y; w[i + 2] = v.z; w[i + 3] = v.w;
+            }
+        } else if constexpr (NW % 2 == 0) {
+#pragma unroll
+            for (int i = 0; i < NW; i += 2) {
+                const uint2 v = *(const uint2 *)(src + 2 * i);
+                w[i] = v.x; w[i + 1] = v.y;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < NW; ++i) w[i] = *(const uint32_t *)(src + 2 * i);
+        }
+        ushort2_t m = __builtin_bit_cast(ushort2_t, w[0]);
+#pragma unroll
+        for (int i = 1; i < NW; ++i) m = __builtin_elementwise_min(m, __builtin_bit_cast(ushort2_t, w[i]));
+        return min((uint32_t)m.x, (uint32_t)m.y);
+    }
+}
+
+// Keeps the compiler from moving LDS accesses across this point; LDS
+// operations of one wavefront are performed in order, so lanes then see each
+// other's earlier writes without a block barrier.
+__device__ __forceinline__ void wave_lds_order()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_wave_barrier();
+    asm volatile("" ::: "memory");
+}
+
+template <int DPL>
+constexpr size_t select_lds_bytes(int W)
+{
+    return (size_t)kSelGroups * kLanesPerLine * DPL * 2 + ((size_t)kLanesPerLine * DPL + W) * 4 + (size_t)W * 6;
+}
+
 template <int DPL, int NDIR, bool SMALL>
 __device__ __forceinline__ void select_row(const SelectArgs &a, int y, uint32_t *smem)
 {
-    const int W = a.W, D = a.D, Dpad = a.Dpad;
-    uint32_t *keyR = smem;                          // W + 1 (the last is a spare slot)
-    float *dsub_row = (float *)(keyR + W + 1);      // W
-    uint8_t *dint_row = (uint8_t *)(dsub_row + W);  // W
-    uint8_t *uniq_row = dint_row + W;               // W
+    constexpr int kDpad = kLanesPerLine * DPL;
+    const int W = a.W, D = a.D;
+    // LDS: per pixel group a row of S (16-bit); right-image keys indexed by
+    // xr + Dpad (xr >= -(Dpad-1)); the row's sub-pixel disparity, d* and
+    // uniqueness flag for the LR pass
+    uint16_t *srow = (uint16_t *)smem;
+    uint32_t *keyR = (uint32_t *)(srow + kSelGroups * kDpad);
+    float *dsub_row = (float *)(keyR + kDpad + W);
+    uint8_t *dint_row = (uint8_t *)(dsub_row + W);
+    uint8_t *uniq_row = dint_row + W;
     const size_t row = (size_t)y * W;
-    for (int x = threadIdx.x; x <= W; x += kSelBlock) keyR[x] = 0xFFFFFFFFu;
+    for (int i = threadIdx.x; i < kDpad + W; i += kSelBlock) keyR[i] = 0xFFFFFFFFu;
     __syncthreads();
 
     const int lane = threadIdx.x % kLanesPerLine, group = threadIdx.x / kLanesPerLine;
     const int d0 = lane * DPL;
+    uint16_t *my = srow + group * kDpad;
     Words<DPL> cur[NDIR], nxt[NDIR];
     if (group < W) {
 #pragma unroll
-        for (int r = 0; r < NDIR; ++r) load_words<DPL>(a.paths[r] + (row + group) * Dpad + d0, cur[r]);
+        for (int r = 0; r < NDIR; ++r) load_words<DPL>(a.paths[r] + (row + group) * kDpad + d0, cur[r]);
     }
     for (int x = group; x < W; x += kSelGroups) {
         const size_t pix = row + x;
         const int xn = x + kSelGroups;
         if (xn < W) {
 #pragma unroll
-            for (int r = 0; r < NDIR; ++r) load_words<DPL>(a.paths[r] + (row + xn) * Dpad + d0, nxt[r]);
+            for (int r = 0; r < NDIR; ++r) load_words<DPL>(a.paths[r] + (row + xn) * kDpad + d0, nxt[r]);
         }
         uint32_t S[DPL];
         sum_paths<DPL, NDIR, SMALL>(cur, S);
+        if (D < kDpad) {
+            // padding disparities: a cost above every real one (real S < 2^11)
+#pragma unroll
+            for (int j = 0; j < DPL; ++j) S[j] = d0 + j < D ? S[j] : 0xFFFFu;
+        }
+        store_row<DPL>(my + d0, S);
 
-        uint32_t key[DPL];
+        // winner key (S << 8 | d): the minimum gives the lowest cost and, among
+        // equal costs, the lowest d; the same key is scattered to xr = x - d
         uint32_t kmin = 0xFFFFFFFFu;
+        const int kb = x - d0 + kDpad - (DPL - 1);  // keyR index of d0 + DPL - 1
 #pragma unroll
         for (int j = 0; j < DPL; ++j) {
-            const int d = d0 + j;
-            key[j] = d < D ? (S[j] << 8) | (uint32_t)d : 0xFFFFFFFFu;
-            kmin = min(kmin, key[j]);
+            const uint32_t key = (S[j] << 8) | (uint32_t)(d0 + j);
+            kmin = min(kmin, key);
+            atomicMin(&keyR[kb + (DPL - 1 - j)], key);
         }
         kmin = row_min(kmin);
         const int dstar = (int)(kmin & 0xFF);
         const uint32_t s1 = kmin >> 8;
-        uint32_t s2 = 0xFFFFFFFFu, nb = 0;
-#pragma unroll
-        for (int j = 0; j < DPL; ++j) {
-            const int d = d0 + j;
-            if (d < D && (d - dstar >= 2 || dstar - d >= 2)) s2 = min(s2, S[j]);
-            if (d == dstar - 1) nb |= S[j] << 16;
-            if (d == dstar + 1 && d < D) nb |= S[j];
-            // no branch: lanes past the left edge hit the spare slot keyR[W], and padding
-            // disparities carry the key 0xFFFFFFFF, for which the minimum is a no-op
-            atomicMin(&keyR[x - d >= 0 ? x - d : W], key[j]);
+        // neighbours for the sub-pixel fit, then the winner's window d*-1 .. d*+1
+        // masked out of the row for the second-best search
+        wave_lds_order();
+        uint32_t nb = 0;
+        if (lane == 0) {
+            if (dstar > 0 && dstar < D - 1) nb = ((uint32_t)my[dstar - 1] << 16) | my[dstar + 1];
+            if (dstar > 0) my[dstar - 1] = 0xFFFFu;
+            my[dstar] = 0xFFFFu;
+            if (dstar + 1 < kDpad) my[dstar + 1] = 0xFFFFu;
         }
-        s2 = row_min(s2);
-        nb = row_or(nb);
+        wave_lds_order();
+        uint32_t s2 = row_min(row_slice_min<DPL>(my + d0));
+        wave_lds_order();
         if (lane == 0) {
             const int u = a.uniqueness_pct;
-            const bool uniq = u == 0 || s2 == 0xFFFFFFFFu || 100u * s1 <= (uint32_t)(100 - u) * s2;
+            const bool uniq = u == 0 || s2 == 0xFFFFu || 100u * s1 <= (uint32_t)(100 - u) * s2;
             float ds = (float)dstar;
             if (a.subpixel && dstar > 0 && dstar < D - 1) {
                 const int am = (int)(nb >> 16) - (int)s1, bp = (int)(nb & 0xFFFF) - (int)s1;
@@ -189,7 +269,7 @@ __device__ __forceinline__ void select_row(const SelectArgs &a, int y, uint32_t 
             }
             a.disp_int[pix] = (uint8_t)dstar;
             a.cost_best[pix] = (uint16_t)s1;
-            a.cost_second[pix] = (uint16_t)min(s2, 0xFFFFu);
+            a.cost_second[pix] = (uint16_t)s2;
             a.disp_sub[pix] = ds;
             dint_row[x] = (uint8_t)dstar;
             dsub_row[x] = ds;
@@ -204,11 +284,11 @@ __device__ __forceinline__ void select_row(const SelectArgs &a, int y, uint32_t 
         const int d = dint_row[x];
         const int xr = x - d;
         bool lr_ok = true;
-        if (lr >= 0) lr_ok = xr >= 0 && abs(d - (int)(keyR[max(xr, 0)] & 0xFF)) <= lr;
+        if (lr >= 0) lr_ok = xr >= 0 && abs(d - (int)(keyR[xr + kDpad] & 0xFF)) <= lr;
         const bool nz = d > 0, uq = uniq_row[x] != 0;
         a.flags[row + x] = (uint8_t)(uq | (lr_ok << 1) | (nz << 2));
         a.masked[row + x] = (uq && lr_ok && nz) ? dsub_row[x] : 0.0f;
-        a.disp_right[row + x] = (uint8_t)(keyR[x] & 0xFF);
+        a.disp_right[row + x] = (uint8_t)(keyR[x + kDpad] & 0xFF);
     }
 }
 
@@ -234,11 +314,11 @@ void launch_sel3(const SelectArgs *a, const SelectBatch *b, bool small, hipStrea
 {
     dim3 block(kSelBlock);
     if (a) {
-        const size_t lds = (size_t)a->W * 10 + 4;
+        const size_t lds = select_lds_bytes<DPL>(a->W);
         if (small) hipLaunchKernelGGL((select_kernel<DPL, NDIR, true>), dim3(a->H), block, lds, s, *a);
         else hipLaunchKernelGGL((select_kernel<DPL, NDIR, false>), dim3(a->H), block, lds, s, *a);
     } else {
-        const size_t lds = (size_t)b->max_width * 10 + 4;
+        const size_t lds = select_lds_bytes<DPL>(b->max_width);
         if (small) hipLaunchKernelGGL((select_batch_kernel<DPL, NDIR, true>), dim3(b->nitems), block, lds, s, *b);
         else hipLaunchKernelGGL((select_batch_kernel<DPL, NDIR, false>), dim3(b->nitems), block, lds, s, *b);
     }

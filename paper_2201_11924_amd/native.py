@@ -144,6 +144,28 @@ class SimSense:
     def shape(self):
         return (self.params["height"], self.params["width"])
 
+    def set_tuning(self, horizontal_lanes: int = 0, blocks_per_cu: int = 3) -> None:
+        """Launch shape of the aggregation (blocks_per_cu 0 = one block per line block)."""
+        t = Tuning(ct.sizeof(Tuning), horizontal_lanes, blocks_per_cu)
+        _check(_lib.simsense_set_tuning(self._h, ct.byref(t)), "simsense_set_tuning")
+
+    def get_tuning(self):
+        t = Tuning()
+        _check(_lib.simsense_get_tuning(self._h, ct.byref(t)), "simsense_get_tuning")
+        return dict(horizontal_lanes=t.horizontal_lanes, blocks_per_cu=t.blocks_per_cu)
+
+    def autotune(self, left: torch.Tensor, right: torch.Tensor, reps: int = 5, stream=None):
+        """Times every launch shape on this pair and keeps the fastest: (best, ms per candidate)."""
+        H, W = self.shape
+        _need(left, torch.uint8, (H, W), "left")
+        _need(right, torch.uint8, (H, W), "right")
+        best = Tuning()
+        ms = (ct.c_float * 32)()
+        count = _i32()
+        _check(_lib.simsense_autotune(self._h, _ptr(left), _ptr(right), W, reps, ct.byref(best), ms, 32,
+                                      ct.byref(count), _stream(stream)), "simsense_autotune")
+        return dict(horizontal_lanes=best.horizontal_lanes, blocks_per_cu=best.blocks_per_cu), list(ms)[:count.value]
+
     def compute(self, left: torch.Tensor, right: torch.Tensor, depth: torch.Tensor,
                 disp: Optional[torch.Tensor] = None, flags: Optional[torch.Tensor] = None, stream=None):
         H, W = self.shape
@@ -221,6 +243,7 @@ _lib.simsense_net_get_grads.argtypes = [_vp, _fp, _i64]
 _lib.simsense_net_forward.argtypes = [_vp, _vp, _i32, _i32, _i32, _vp, _vp]
 _lib.simsense_net_train_step.argtypes = [_vp, _vp, _vp, _vp, _i32, _i32, _i32, ct.c_float, _vp, _vp]
 _lib.simsense_net_targets.argtypes = [_vp, _vp, _vp, _vp, _vp, _i64, _vp]
+_lib.simsense_net_infer.argtypes = [_vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, ct.c_float, _vp, _vp]
 _lib.simsense_learned_compute.argtypes = [_vp, _vp, _vp, _vp, _i32, ct.POINTER(Outputs), _vp]
 
 NUM_NET_PARAMS = int(_lib.simsense_net_num_params())
@@ -283,6 +306,27 @@ class Net:
                "simsense_net_forward")
         return out
 
+    def infer(self, features: torch.Tensor, d2_sub: Optional[torch.Tensor] = None, raw: bool = True,
+              tau: float = 0.0, uncertain: Optional[torch.Tensor] = None, stream=None):
+        """Fused inference: {"out": [B,H,W,2] (if raw), "masked", "flags" (if d2_sub is given)}."""
+        B, H, W, C = features.shape
+        if C != 8 or features.element_size() != 2 or not features.is_contiguous():
+            raise ValueError("features: contiguous 16-bit [B, H, W, 8] tensor (bf16 bits)")
+        dev = features.device
+        res = {}
+        if raw:
+            res["out"] = torch.empty((B, H, W, 2), dtype=torch.float32, device=dev)
+        if d2_sub is not None:
+            _need(d2_sub, torch.float32, (B, H, W), "d2_sub")
+            res["masked"] = torch.empty((B, H, W), dtype=torch.float32, device=dev)
+            res["flags"] = torch.empty((B, H, W), dtype=torch.uint8, device=dev)
+        if uncertain is not None:
+            _need(uncertain, torch.int32, (B,), "uncertain")
+        _check(_lib.simsense_net_infer(self._h, _ptr(features), B, H, W, _ptr(d2_sub), _ptr(res.get("out")),
+                                       _ptr(res.get("masked")), _ptr(res.get("flags")), float(tau),
+                                       _ptr(uncertain), _stream(stream)), "simsense_net_infer")
+        return res
+
     def train_step(self, features: torch.Tensor, t_res: torch.Tensor, t_valid: torch.Tensor, lr: float,
                    stream=None) -> torch.Tensor:
         B, H, W, C = features.shape
@@ -331,6 +375,10 @@ class Tuning(ct.Structure):
     _fields_ = [("struct_size", ct.c_uint32), ("horizontal_lanes", _i32), ("blocks_per_cu", _i32)]
 
 
+_lib.simsense_set_tuning.argtypes = [_vp, ct.POINTER(Tuning)]
+_lib.simsense_get_tuning.argtypes = [_vp, ct.POINTER(Tuning)]
+_lib.simsense_autotune.argtypes = [_vp, _vp, _vp, _i32, _i32, ct.POINTER(Tuning), ct.POINTER(ct.c_float), _i32,
+                                   ct.POINTER(_i32), _vp]
 _lib.simsense_batch_create.argtypes = [ct.POINTER(Params), _i32, ct.POINTER(_vp)]
 _lib.simsense_batch_destroy.argtypes = [_vp]
 _lib.simsense_batch_scratch_bytes.argtypes = [_vp]

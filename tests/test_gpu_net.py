@@ -161,3 +161,34 @@ def test_features_and_learned_path_match_oracle(nat, orc):
     assert np.mean(np.abs(dg[both] - disp_ref[both]) <= 0.05) >= 0.99
     ss.close()
     net.close()
+
+
+@pytest.mark.parametrize("B,H,W", [(2, 200, 250), (1, 5, 7), (3, 91, 81), (1, 1, 300), (1, 181, 1)])
+def test_fused_inference_equals_layered_forward(nat, B, H, W):
+    """The fused kernel (row-strip LDS rings, several strips and row segments
+    with ragged tails) gives the per-layer forward's outputs bit for bit, and
+    its combination and uncertainty counts equal a host recomputation."""
+    import torch
+    x, params, _, _ = random_case(100 + B * H + W, B, H, W)
+    net = nat.Net(B * H * W, seed=3)
+    net.set_state(no.flatten(params))
+    feats = dev(bf16_bits(x)).view(torch.int16)
+    ref = net.forward(feats).cpu().numpy()
+    rng = np.random.default_rng(H * W)
+    d2 = rng.uniform(-2.0, 40.0, (B, H, W)).astype(np.float32)
+    unc = torch.full((B,), 5, dtype=torch.int32, device="cuda")
+    tau = 0.3
+    got = net.infer(feats, d2_sub=dev(d2), tau=tau, uncertain=unc)
+    out = got["out"].cpu().numpy()
+    assert np.array_equal(out.view(np.uint32), ref.view(np.uint32))
+    d = (d2 + ref[..., 0]).astype(np.float32)
+    ok = (ref[..., 1] > 0) & (d > 0)
+    assert np.array_equal(got["masked"].cpu().numpy(), np.where(ok, d, np.float32(0)))
+    assert np.array_equal(got["flags"].cpu().numpy(), np.where(ok, 7, 0).astype(np.uint8))
+    want = 5 + (np.abs(ref[..., 1]) < tau).reshape(B, -1).sum(1)
+    assert np.array_equal(unc.cpu().numpy(), want)
+    # outputs are optional: raw only, then the combination only
+    assert "masked" not in net.infer(feats)
+    only = net.infer(feats, d2_sub=dev(d2), raw=False)
+    assert "out" not in only and torch.equal(only["masked"], got["masked"])
+    net.close()

@@ -145,3 +145,37 @@ def test_c1_like_other_sizes(orc, nat):
         cfg = c1_like(W, H, D)
         left, right = noisy_pair(orc, cfg["spec"], W + D)
         compare(orc, nat, cfg["params"], left, right, label=f"{W}x{H}")
+
+
+@pytest.mark.parametrize("W,H,D,paths", [(173, 61, 64, 8), (90, 77, 96, 4), (64, 33, 128, 2)])
+def test_every_launch_shape_matches_oracle(orc, nat, W, H, D, paths):
+    """Both aggregation launch forms (one block per line block, persistent grid)
+    and every lane count give the oracle's results; autotune keeps the fastest."""
+    import torch
+    spec = PairSpec(W, H, planes=3, dmin=0, dmax=min(D - 1, W - 1) * 0.8, noise="gauss", sigma=3.0)
+    left, right = noisy_pair(orc, spec, 7 * W + H)
+    params = params_for(W, H, D, num_paths=paths)
+    ref = orc.sgm(params, left, right)
+    ss = nat.SimSense(params)
+    assert ss.get_tuning() == dict(horizontal_lanes=0, blocks_per_cu=3)
+    L, R = dev(left), dev(right)
+    Dpad = 16 * next(o for o in (1, 2, 4, 6, 8, 12, 16) if 16 * o >= D)
+    lanes = [hl for hl in (16, 32, 64) if Dpad % hl == 0]
+    for hl in lanes:
+        for bpc in (0, 1, 3, 8):
+            ss.set_tuning(hl, bpc)
+            depth, disp, flags = ss(L, R)
+            torch.cuda.synchronize()
+            assert np.array_equal(host(flags), ref.flags), (hl, bpc)
+            assert np.allclose(host(disp), ref.disp, rtol=0, atol=DISP_TOL), (hl, bpc)
+    best, ms = ss.autotune(L, R, reps=2)
+    assert len(ms) == 5 * len(lanes) and all(m > 0 for m in ms)
+    assert best["horizontal_lanes"] in lanes and 0 <= best["blocks_per_cu"] <= 4
+    assert ss.get_tuning() == best
+    depth, disp, flags = ss(L, R)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(flags), ref.flags)
+    for bad in ((48, 1), (16, 9), (16, -1)):
+        with pytest.raises(nat.SimSenseError):
+            ss.set_tuning(*bad)
+    ss.close()
