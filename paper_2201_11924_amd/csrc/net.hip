@@ -24,12 +24,15 @@ namespace net {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ uint16_t f2bf(float f)
+// fp32 -> bf16, round to nearest even (the gfx950 conversion instruction)
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+// two values as one packed word, the first in the low half (v_cvt_pk_bf16_f32)
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi)
 {
-    // round to nearest, ties to even (inputs here are finite)
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    const bf16x2_t v = {(__bf16)lo, (__bf16)hi};
+    return __builtin_bit_cast(uint32_t, v);
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
@@ -110,7 +113,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a)
                     o[1] = acc[mb][1] + bias[mb][1];
                 }
             } else {
-                uint16_t h[4];
+                float h[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     float v = acc[mb][i];
@@ -120,11 +123,11 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a)
                         const uint16_t mk = a.mask[p * COUTP + co + i];
                         v = (mk & 0x7FFF) != 0 && !(mk & 0x8000) ? v : 0.0f;  // mask > 0
                     }
-                    h[i] = f2bf(v);
+                    h[i] = v;
                 }
                 uint2 w;
-                w.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
-                w.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
+                w.x = pack_bf16(h[0], h[1]);
+                w.y = pack_bf16(h[2], h[3]);
                 *(uint2 *)((uint16_t *)a.out + p * COUTP + co) = w;
             }
         }
@@ -337,7 +340,7 @@ __global__ __launch_bounds__(256) void loss_kernel(LossArgs a)
         bce += fmaxf(z, 0.0f) - z * v + log1pf(expf(-fabsf(z)));
         const float dr = (e > 0.0f ? 1.0f : (e < 0.0f ? -1.0f : 0.0f)) * v * inv_nv;
         const float dz = (1.0f / (1.0f + expf(-z)) - v) * inv_n;
-        uint4 w = make_uint4((uint32_t)f2bf(dr) | ((uint32_t)f2bf(dz) << 16), 0, 0, 0);
+        uint4 w = make_uint4(pack_bf16(dr, dz), 0, 0, 0);
         uint4 *dst = (uint4 *)(a.dy + p * 16);
         dst[0] = w;
         dst[1] = make_uint4(0, 0, 0, 0);
@@ -458,8 +461,8 @@ __global__ __launch_bounds__(256) void features_kernel(FeatureArgs a)
     const float s2 = s2r == 0xFFFFu ? a.smax : fminf((float)s2r, a.smax);
     const float f0 = ir / 255.0f, f1 = s1 / a.smax, f2 = s2 / a.smax, f3 = (float)a.dint[p] / (float)a.max_disp;
     uint4 w;
-    w.x = (uint32_t)f2bf(f0) | ((uint32_t)f2bf(f1) << 16);
-    w.y = (uint32_t)f2bf(f2) | ((uint32_t)f2bf(f3) << 16);
+    w.x = pack_bf16(f0, f1);
+    w.y = pack_bf16(f2, f3);
     w.z = 0;
     w.w = 0;
     *(uint4 *)(a.features + p * 8) = w;

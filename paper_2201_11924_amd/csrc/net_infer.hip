@@ -35,11 +35,12 @@ constexpr int kOutTiles = kOutW / 16;
 static_assert(kOutW % 16 == 0, "output strip must be whole tiles");
 static_assert(kHalo + kOutW + kHalo <= kRingW, "ring too narrow for the halo");
 
-__device__ __forceinline__ uint16_t f2bf(float f)
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+// two values as one packed word, the first in the low half (v_cvt_pk_bf16_f32)
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi)
 {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    const bf16x2_t v = {(__bf16)lo, (__bf16)hi};
+    return __builtin_bit_cast(uint32_t, v);
 }
 
 __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v)
@@ -127,15 +128,12 @@ __device__ __forceinline__ void layer_row(Smem &sm, const bf16x8 (&wa)[2][9], in
         const bool inside = x >= 0 && x < W;
         const float4 bv = sm.bias[out_layer][4 * mb + quad];  // channels 16 mb + 4 quad .. +3
         const float bias[4] = {bv.x, bv.y, bv.z, bv.w};
-        uint16_t h[4];
+        float v[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const uint16_t v = f2bf(fmaxf(acc[i][e] + bias[e], 0.0f));
-            h[e] = inside ? v : (uint16_t)0;
-        }
+        for (int e = 0; e < 4; ++e) v[e] = inside ? fmaxf(acc[i][e] + bias[e], 0.0f) : 0.0f;
         uint2 w;
-        w.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
-        w.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
+        w.x = pack_bf16(v[0], v[1]);
+        w.y = pack_bf16(v[2], v[3]);
         uint2 *dst = (uint2 *)&sm.act[out_layer][slot][q + 1][0] + (16 * mb + 4 * quad) / 4;
         *dst = w;
     }
