@@ -50,6 +50,38 @@ def parse():
     return ap.parse_args()
 
 
+AGG_SOURCES = ("aggregate_impl.h", "aggregate.hip", "agg_dpl8.hip")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "aggregate_queue_1280x720_d128_8path_traffic.md")
+
+
+def aggregation_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in AGG_SOURCES:
+        with open(os.path.join(ROOT, "paper_2201_11924_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per aggregation launch from the committed counter summary, or None
+    when the aggregation sources have changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    fields = {}
+    with open(TRAFFIC_PROFILE) as f:
+        for line in f:
+            if ":" in line and line.startswith("- `"):
+                k, v = line[3:].split("`", 1)[0], line.split(":", 1)[1].strip()
+                fields[k] = v
+    if fields.get("source_sha256") != aggregation_source_hash():
+        return None
+    try:
+        return int(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(params, left, right, rows):
     """The oracle as it stands, one host thread, on a bounded sample of the workload."""
     from oracle import oracle as orc
@@ -150,6 +182,7 @@ def learned_and_batch_legs(nat, args, out, inputs):
     # learned form, every pair in one graph launch
     b2 = nat.Batch([params2] * npairs)
     outs2 = b2.outputs()
+    tune2, _ = b2.autotune(Ls, Rs, outs2, reps=2)  # launch shape for the 2-path matching
     unc = torch.zeros(npairs, dtype=torch.int32, device="cuda")
     tau = 0.5
     b2.learned_compute(net, Ls, Rs, outs2, tau, unc)
@@ -174,7 +207,7 @@ def learned_and_batch_legs(nat, args, out, inputs):
     res["batch_256_sensor"] = {
         "pairs": npairs, "plain_8path_pairs_s": round(pairs8, 2), "learned_2path_net_pairs_s": round(pairs2, 2),
         "speedup": round(pairs2 / pairs8, 3), "plain_graph_launches": (npairs + g8 - 1) // g8,
-        "learned_graph_launches": 1, "net_trained": trained,
+        "learned_graph_launches": 1, "net_trained": trained, "learned_tuning": tune2,
         "quality_vs_8path": qm, "fallback": {"tau": tau, "threshold_frac": args.fallback_frac,
                                              "rate": round(float(fall.mean()), 4),
                                              "quality_after_fallback": qm_after},
@@ -303,9 +336,10 @@ def main():
     agg_s = pass_ms["aggregate"] / calls / 1000.0
     agg_ops = AGG_OPS_PER_PDR * P * vol
     achieved = agg_ops / agg_s
-    roofline = {"kernel": "aggregate_kernel", "bound": "alu", "achieved": round(achieved / 1e12, 3),
+    kernel = "aggregate_queue_kernel" if ss.get_tuning()["blocks_per_cu"] > 0 else "aggregate_kernel"
+    roofline = {"kernel": kernel, "bound": "alu", "achieved": round(achieved / 1e12, 3),
                 "peak": round(VALU_PEAK_OPS / 1e12, 3), "unit": "Tops/s", "frac": round(achieved / VALU_PEAK_OPS, 4),
-                "traffic": None,
+                "traffic": measured_traffic(),
                 "ops_per_launch": agg_ops, "avg_launch_us": round(agg_s * 1e6, 2)}
     out = {
         "metric": "stereo pairs/sec & Mpix·disp/s at 1280×720 D=128: 8-path SGM vs 2-path+net",

@@ -189,7 +189,7 @@ __device__ __forceinline__ void wave_lds_order()
 template <int DPL>
 constexpr size_t select_lds_bytes(int W)
 {
-    return (size_t)kSelGroups * kLanesPerLine * DPL * 2 + ((size_t)kLanesPerLine * DPL + W) * 4 + (size_t)W * 6;
+    return (size_t)kSelGroups * kLanesPerLine * DPL * 2 + ((size_t)kLanesPerLine * DPL + W) * 4 + (size_t)W * 10;
 }
 
 template <int DPL, int NDIR, bool SMALL>
@@ -198,12 +198,15 @@ __device__ __forceinline__ void select_row(const SelectArgs &a, int y, uint32_t 
     constexpr int kDpad = kLanesPerLine * DPL;
     const int W = a.W, D = a.D;
     // LDS: per pixel group a row of S (16-bit); right-image keys indexed by
-    // xr + Dpad (xr >= -(Dpad-1)); the row's sub-pixel disparity, d* and
-    // uniqueness flag for the LR pass
+    // xr + Dpad (xr >= -(Dpad-1)); the row's per-pixel results, written to HBM
+    // in coalesced row stores after the pixel loop (the loop itself issues no
+    // global store, so its look-ahead loads are waited on precisely)
     uint16_t *srow = (uint16_t *)smem;
     uint32_t *keyR = (uint32_t *)(srow + kSelGroups * kDpad);
     float *dsub_row = (float *)(keyR + kDpad + W);
-    uint8_t *dint_row = (uint8_t *)(dsub_row + W);
+    uint16_t *s1_row = (uint16_t *)(dsub_row + W);
+    uint16_t *s2_row = s1_row + W;
+    uint8_t *dint_row = (uint8_t *)(s2_row + W);
     uint8_t *uniq_row = dint_row + W;
     const size_t row = (size_t)y * W;
     for (int i = threadIdx.x; i < kDpad + W; i += kSelBlock) keyR[i] = 0xFFFFFFFFu;
@@ -218,12 +221,10 @@ __device__ __forceinline__ void select_row(const SelectArgs &a, int y, uint32_t 
         for (int r = 0; r < NDIR; ++r) load_words<DPL>(a.paths[r] + (row + group) * kDpad + d0, cur[r]);
     }
     for (int x = group; x < W; x += kSelGroups) {
-        const size_t pix = row + x;
-        const int xn = x + kSelGroups;
-        if (xn < W) {
+        // look-ahead loads are unconditional (clamped to the row's last pixel)
+        const int xn = min(x + kSelGroups, W - 1);
 #pragma unroll
-            for (int r = 0; r < NDIR; ++r) load_words<DPL>(a.paths[r] + (row + xn) * kDpad + d0, nxt[r]);
-        }
+        for (int r = 0; r < NDIR; ++r) load_words<DPL>(a.paths[r] + (row + xn) * kDpad + d0, nxt[r]);
         uint32_t S[DPL];
         sum_paths<DPL, NDIR, SMALL>(cur, S);
         if (D < kDpad) {
@@ -267,10 +268,8 @@ __device__ __forceinline__ void select_row(const SelectArgs &a, int y, uint32_t 
                 const int am = (int)(nb >> 16) - (int)s1, bp = (int)(nb & 0xFFFF) - (int)s1;
                 ds = __fadd_rn((float)dstar, __fdiv_rn((float)(am - bp), (float)(2 * (am + bp))));
             }
-            a.disp_int[pix] = (uint8_t)dstar;
-            a.cost_best[pix] = (uint16_t)s1;
-            a.cost_second[pix] = (uint16_t)s2;
-            a.disp_sub[pix] = ds;
+            s1_row[x] = (uint16_t)s1;
+            s2_row[x] = (uint16_t)s2;
             dint_row[x] = (uint8_t)dstar;
             dsub_row[x] = ds;
             uniq_row[x] = uniq;
@@ -289,6 +288,10 @@ __device__ __forceinline__ void select_row(const SelectArgs &a, int y, uint32_t 
         a.flags[row + x] = (uint8_t)(uq | (lr_ok << 1) | (nz << 2));
         a.masked[row + x] = (uq && lr_ok && nz) ? dsub_row[x] : 0.0f;
         a.disp_right[row + x] = (uint8_t)(keyR[x + kDpad] & 0xFF);
+        a.disp_int[row + x] = (uint8_t)d;
+        a.cost_best[row + x] = s1_row[x];
+        a.cost_second[row + x] = s2_row[x];
+        a.disp_sub[row + x] = dsub_row[x];
     }
 }
 

@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -120,7 +121,15 @@ def build_dataset(runner: PairRunner, raws: List) -> Dict:
     return dict(features=torch.stack(feats), t_res=torch.stack(tres), t_valid=torch.stack(tval))
 
 
-def train(net, data: Dict, steps: int, batch: int, lr: float, seed: int = 0, log=None) -> List[float]:
+def lr_at(it: int, steps: int, lr: float, schedule: str, min_lr: float) -> float:
+    """Learning rate of step `it`: constant, or cosine decay from lr to min_lr."""
+    if schedule == "cosine" and steps > 1:
+        return min_lr + 0.5 * (lr - min_lr) * (1.0 + math.cos(math.pi * it / (steps - 1)))
+    return lr
+
+
+def train(net, data: Dict, steps: int, batch: int, lr: float, seed: int = 0, log=None, schedule: str = "constant",
+          min_lr: float = 0.0) -> List[float]:
     import torch
     n = data["features"].shape[0]
     rng = np.random.default_rng(seed)
@@ -136,7 +145,7 @@ def train(net, data: Dict, steps: int, batch: int, lr: float, seed: int = 0, log
         f = data["features"].index_select(0, idx).contiguous()
         t = data["t_res"].index_select(0, idx).contiguous()
         v = data["t_valid"].index_select(0, idx).contiguous()
-        loss = net.train_step(f, t, v, lr)
+        loss = net.train_step(f, t, v, lr_at(it, steps, lr, schedule, min_lr))
         if log is not None and (it % 25 == 0 or it == steps - 1):
             lv = loss.cpu().numpy()
             losses.append(float(lv[0]))
@@ -167,6 +176,8 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--schedule", choices=("constant", "cosine"), default="constant")
+    ap.add_argument("--min-lr", type=float, default=1e-5)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--workers", type=int, default=12)
     ap.add_argument("--out", default=None, help="checkpoint path")
@@ -194,7 +205,7 @@ def main(argv=None):
         load_checkpoint(args.resume, net)
     before = evaluate(nat, runner, net, eval_raw)
     t0 = time.time()
-    losses = train(net, data, args.steps, args.batch, args.lr, args.seed, log)
+    losses = train(net, data, args.steps, args.batch, args.lr, args.seed, log, args.schedule, args.min_lr)
     torch.cuda.synchronize()
     train_s = time.time() - t0
     after = evaluate(nat, runner, net, eval_raw)
@@ -204,6 +215,7 @@ def main(argv=None):
     log(json.dumps(res))
     if args.out:
         save_checkpoint(args.out, net, dict(pairs=args.pairs, steps=args.steps, batch=args.batch, lr=args.lr,
+                                            schedule=args.schedule, min_lr=args.min_lr, resumed_from=args.resume,
                                             width=args.width, height=args.height, max_disp=args.max_disp))
     runner.close()
     net.close()
