@@ -356,6 +356,19 @@ def main():
         "roofline": roofline,
     }
     ss.close()
+    if not args.no_paper_shape:
+        # the same pair with the LR check against a full right-referenced run
+        ssr = nat.SimSense(dict(params, lr_mode=1))
+        for _ in range(5):
+            ssr.compute(L, R, depth, disp, flags)
+        start.record()
+        for _ in range(50):
+            ssr.compute(L, R, depth, disp, flags)
+        end.record()
+        torch.cuda.synchronize()
+        msr = start.elapsed_time(end) / 50
+        ssr.close()
+        out["lr_full_right_run"] = {"pairs_s": round(1000.0 / msr, 2), "ms": round(msr, 4)}
     if args.calibration_copy_mb > 0:
         n = args.calibration_copy_mb << 20
         src = torch.empty(n, dtype=torch.uint8, device=dev).fill_(1)

@@ -60,6 +60,11 @@ typedef enum simsense_status {
  *  median           0 (off) or 3 (3x3 median of the masked disparity map).
  *  subpixel         0 or 1 (quadratic fit through d*-1, d*, d*+1).
  *  focal_px         focal length in pixels; baseline_m  stereo baseline (depth is in its unit).
+ *  lr_mode          right-image disparity of the left-right check (Sec. VI-D names the check,
+ *                   not how the right disparity is found): 0 = read off the left-referenced
+ *                   volume, dR(xr) = argmin_d S(xr+d, d); 1 = a full right-referenced SGM run
+ *                   (cost of right pixel xr against left pixel xr+d, the same paths and
+ *                   penalties), which doubles the matching work.  Batches support 0 only.
  */
 typedef struct simsense_params {
     uint32_t struct_size;
@@ -69,6 +74,7 @@ typedef struct simsense_params {
     int32_t uniqueness_pct, lr_max_diff;
     int32_t num_paths, median, subpixel;
     float focal_px, baseline_m;
+    int32_t lr_mode;
 } simsense_params;
 
 /* Bits of the per-pixel flag byte written by the compute calls. */
@@ -134,7 +140,10 @@ int simsense_census(const simsense_params *params, const uint8_t *img, int32_t p
  * aggregation, selection, post-processing).  simsense_profile_read waits for
  * the recorded events, writes the accumulated milliseconds of pass i to ms[i]
  * and the number of timed calls to *calls (both for at most n passes), and
- * resets the accumulators.  Events are created by the enable call. */
+ * resets the accumulators.  Events are created by the enable call.  With
+ * lr_mode 1 the aggregation pass times the left-referenced aggregation and the
+ * selection pass everything after it (left selection, the right-referenced
+ * aggregation and selection, and the check). */
 #define SIMSENSE_PASS_CENSUS 0
 #define SIMSENSE_PASS_AGGREGATE 1
 #define SIMSENSE_PASS_SELECT 2

@@ -47,7 +47,7 @@ class OrcParams(ct.Structure):
     _fields_ = [(n, ct.c_int32) for n in (
         "width", "height", "max_disp", "census_w", "census_h", "census_mode", "p1", "p2",
         "uniqueness_pct", "lr_max_diff", "num_paths", "median", "subpixel")] + [
-        ("focal_px", ct.c_float), ("baseline_m", ct.c_float)]
+        ("focal_px", ct.c_float), ("baseline_m", ct.c_float), ("lr_mode", ct.c_int32)]
 
 
 class OrcResult(ct.Structure):
@@ -139,6 +139,24 @@ def right_disp(S: np.ndarray) -> np.ndarray:
     return dR
 
 
+def cost_right(cl: np.ndarray, cr: np.ndarray, D: int, bits: int) -> np.ndarray:
+    cl = np.ascontiguousarray(cl, np.uint64)
+    cr = np.ascontiguousarray(cr, np.uint64)
+    H, W = cl.shape
+    C = np.empty((H, W, D), np.uint8)
+    lib().orc_cost_right(_p(cl), _p(cr), W, H, D, bits, _p(C))
+    return C
+
+
+def right_disp_full(cl: np.ndarray, cr: np.ndarray, D: int, bits: int, num_paths: int, p1: int, p2: int):
+    cl = np.ascontiguousarray(cl, np.uint64)
+    cr = np.ascontiguousarray(cr, np.uint64)
+    H, W = cl.shape
+    dR = np.empty((H, W), np.int32)
+    lib().orc_right_disp_full(_p(cl), _p(cr), W, H, D, bits, num_paths, p1, p2, _p(dR))
+    return dR
+
+
 def lr_check(dint: np.ndarray, dR: np.ndarray, lr: int) -> np.ndarray:
     dint = np.ascontiguousarray(dint, np.int32)
     dR = np.ascontiguousarray(dR, np.int32)
@@ -186,7 +204,7 @@ def sgm(params: dict, left: np.ndarray, right: np.ndarray, keep_volume: bool = F
     H, W = left.shape
     assert params["width"] == W and params["height"] == H
     D = params["max_disp"]
-    pp = OrcParams(**{k: params[k] for k, _ in OrcParams._fields_})
+    pp = OrcParams(**{k: params.get(k, 0) if k == "lr_mode" else params[k] for k, _ in OrcParams._fields_})
     arrs = dict(census_l=np.empty((H, W), np.uint64), census_r=np.empty((H, W), np.uint64),
                 S=np.empty((H, W, D), np.uint32) if keep_volume else None,
                 dint=np.empty((H, W), np.int32), s1=np.empty((H, W), np.int32),

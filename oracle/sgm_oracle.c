@@ -22,7 +22,8 @@
  *  - path recurrence in its normalised form, first pixel of a path L = C.
  *  - winner: lowest d on ties; uniqueness second best over |d-d*| >= 2,
  *    valid iff 100*S1 <= (100-u)*S2; sub-pixel parabola through d*-1, d*, d*+1;
- *    right disparity from the left volume, LR on integer disparities;
+ *    right disparity from the left volume (or, as an option, from a full
+ *    right-referenced run), LR on integer disparities;
  *    d* = 0 is invalid; 3x3 median on the masked map with the border copied;
  *    depth = f*B/d.
  */
@@ -212,6 +213,41 @@ void orc_right_disp(const uint32_t *S, int W, int H, int D, int32_t *dR)
         }
 }
 
+/* Right-referenced matching cost: the right pixel xr against the left pixel
+ * xr + d, CR[(y*W + xr)*D + d] = popcount(cR(xr,y) ^ cL(xr+d,y)), and the number
+ * of census bits where xr + d > W-1. */
+void orc_cost_right(const uint64_t *cl, const uint64_t *cr, int W, int H, int D, int bits, uint8_t *CR)
+{
+    for (int y = 0; y < H; ++y)
+        for (int xr = 0; xr < W; ++xr)
+            for (int d = 0; d < D; ++d) {
+                int c = bits;
+                if (xr + d <= W - 1) c = orc_popcount(cr[(size_t)y * W + xr] ^ cl[(size_t)y * W + xr + d]);
+                CR[((size_t)y * W + xr) * D + d] = (uint8_t)c;
+            }
+}
+
+/* Right disparity from a full right-referenced SGM run: the right-referenced
+ * cost aggregated over the same paths with the same penalties, then the winner
+ * of each right pixel (lowest d on ties). */
+void orc_right_disp_full(const uint64_t *cl, const uint64_t *cr, int W, int H, int D, int bits, int num_paths,
+                         int P1, int P2, int32_t *dR)
+{
+    size_t n = (size_t)W * H * D;
+    uint8_t *CR = (uint8_t *)malloc(n);
+    uint32_t *SR = (uint32_t *)malloc(n * sizeof(uint32_t));
+    orc_cost_right(cl, cr, W, H, D, bits, CR);
+    orc_aggregate(CR, W, H, D, num_paths, P1, P2, SR);
+    for (size_t p = 0; p < (size_t)W * H; ++p) {
+        int best = 0;
+        for (int d = 1; d < D; ++d)
+            if (SR[p * D + d] < SR[p * D + best]) best = d;
+        dR[p] = best;
+    }
+    free(CR);
+    free(SR);
+}
+
 /* Left-right consistency on integer disparities:
  *   valid iff lr < 0, or x - d* >= 0 and |d* - dR(x - d*)| <= lr. */
 void orc_lr_check(const int32_t *dint, const int32_t *dR, int W, int H, int lr, uint8_t *valid_lr)
@@ -263,6 +299,7 @@ typedef struct orc_params {
     int32_t census_w, census_h, census_mode;
     int32_t p1, p2, uniqueness_pct, lr_max_diff, num_paths, median, subpixel;
     float focal_px, baseline_m;
+    int32_t lr_mode; /* 0: right disparity read off the left volume; 1: full right-referenced run */
 } orc_params;
 
 typedef struct orc_result {
@@ -290,7 +327,10 @@ int orc_sgm(const orc_params *pp, const uint8_t *left, const uint8_t *right, orc
     orc_cost(r->census_l, r->census_r, W, H, D, bits, C);
     orc_aggregate(C, W, H, D, pp->num_paths, pp->p1, pp->p2, S);
     orc_wta(S, W, H, D, pp->uniqueness_pct, pp->subpixel, r->dint, r->s1, r->s2, vu, r->dsub);
-    orc_right_disp(S, W, H, D, r->dright);
+    if (pp->lr_mode == 1)
+        orc_right_disp_full(r->census_l, r->census_r, W, H, D, bits, pp->num_paths, pp->p1, pp->p2, r->dright);
+    else
+        orc_right_disp(S, W, H, D, r->dright);
     orc_lr_check(r->dint, r->dright, W, H, pp->lr_max_diff, vlr);
     for (size_t p = 0; p < npx; ++p) {
         int nz = r->dint[p] > 0;

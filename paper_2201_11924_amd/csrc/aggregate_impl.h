@@ -131,6 +131,19 @@ struct CensusWord<true> {
     static __device__ __forceinline__ uint32_t hamming(T a, T b) { return __popcll(a ^ b); }
 };
 
+// Path-value stores go through global-address-space pointers: a generic (flat)
+// store would also count against the LDS counter and make every wait for a
+// census read from LDS wait for the outstanding stores as well.
+template <typename T>
+__device__ __forceinline__ void gstore(uint8_t *p, T v)
+{
+    *(__attribute__((address_space(1))) T *)p = v;
+}
+// (native vector types: HIP's uint2/uint4 classes assign through a generic
+// `this` pointer, which would turn the store back into a flat one)
+typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
 template <int DPL>
 __device__ __forceinline__ void store_bytes(uint8_t *dst, const uint32_t (&L)[DPL])
 {
@@ -144,23 +157,23 @@ __device__ __forceinline__ void store_bytes(uint8_t *dst, const uint32_t (&L)[DP
             w[k] = __builtin_amdgcn_perm(hi, lo, 0x05040100u);
         }
         if constexpr (DPL == 4) {
-            *(uint32_t *)dst = w[0];
+            gstore(dst, w[0]);
         } else if constexpr (DPL == 8) {
-            *(uint2 *)dst = make_uint2(w[0], w[1]);
+            gstore(dst, u32x2_t{w[0], w[1]});
         } else if constexpr (DPL == 12) {
-            *(uint2 *)dst = make_uint2(w[0], w[1]);
-            *(uint32_t *)(dst + 8) = w[2];
+            gstore(dst, u32x2_t{w[0], w[1]});
+            gstore(dst + 8, w[2]);
         } else {
             static_assert(DPL == 16, "unsupported disparities per lane");
-            *(uint4 *)dst = make_uint4(w[0], w[1], w[2], w[3]);
+            gstore(dst, u32x4_t{w[0], w[1], w[2], w[3]});
         }
     } else if constexpr (DPL % 2 == 0) {
 #pragma unroll
         for (int k = 0; k < DPL / 2; ++k)
-            *(uint16_t *)(dst + 2 * k) = (uint16_t)((L[2 * k] & 0xFF) | ((L[2 * k + 1] & 0xFF) << 8));
+            gstore(dst + 2 * k, (uint16_t)((L[2 * k] & 0xFF) | ((L[2 * k + 1] & 0xFF) << 8)));
     } else {
 #pragma unroll
-        for (int k = 0; k < DPL; ++k) dst[k] = (uint8_t)L[k];
+        for (int k = 0; k < DPL; ++k) gstore(dst + k, (uint8_t)L[k]);
     }
 }
 
@@ -264,9 +277,27 @@ __device__ __forceinline__ void window_at(const BlockGeom &g, int t, int &row, i
 // line's first pixel, exactly the state a line starts from.  Lanes of lines that
 // have ended (or not started) store into one spare pixel after the image, so
 // every step issues the same unconditional store.
+// The scalars one block of lines needs, each made explicitly wavefront-uniform
+// (readfirstlane) so that they live in scalar registers even when they were read
+// from a work list in memory, which the compiler cannot prove uniform.
+struct LineArgs {
+    const uint32_t *cl, *cr;  // census words (dwords; two per word when 64-bit)
+    uint8_t *out;             // this direction's path values
+    int W, H, D, p1, p2, bits;
+};
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+template <typename T>
+__device__ __forceinline__ T *uniform(T *p)
+{
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v), hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (T *)(((uint64_t)hi << 32) | lo);
+}
+
 template <int DPL, int LPL, bool WIDE, bool HORIZ, int TILE>
-__device__ __forceinline__ void run_lines(const AggregateArgs &a, const BlockGeom &g, uint8_t *__restrict__ out,
-                                          uint32_t (*tile)[TILE])
+__device__ __forceinline__ void run_lines(const LineArgs &a, const BlockGeom &g, uint32_t (*tile)[TILE])
 {
     using CW = CensusWord<WIDE>;
     using LO = LineOps<LPL>;
@@ -284,8 +315,9 @@ __device__ __forceinline__ void run_lines(const AggregateArgs &a, const BlockGeo
     const int lane = threadIdx.x % LPL, li = threadIdx.x / LPL;
     const bool first = lane == 0, last = lane == LPL - 1;
     const int d0 = lane * DPL;
-    const uint32_t *__restrict__ cl = (const uint32_t *)a.census_l;
-    const uint32_t *__restrict__ cr = (const uint32_t *)a.census_r;
+    const uint32_t *__restrict__ cl = a.cl;
+    const uint32_t *__restrict__ cr = a.cr;
+    uint8_t *__restrict__ out = a.out;
     const uint32_t p1 = a.p1, p2 = a.p2, bits = a.bits;
     const bool padded = D < kDpad;
     const size_t trash = (size_t)W * H * kDpad + d0;
@@ -459,19 +491,26 @@ __device__ __forceinline__ void aggregate_block(const AggregateArgs &a, int blk,
     constexpr int kDpad = kLanesPerLine * DPL;
     static_assert(kDpad % HL == 0, "horizontal lanes must divide the padded disparity count");
     int dir = 0;
+    const int ndirs = uniform(a.ndirs);
 #pragma unroll
     for (int k = 1; k < 8; ++k)
-        if (k < a.ndirs && blk >= a.block_begin[k]) dir = k;
-    const BlockGeom g = block_geometry(a.dx[dir], a.dy[dir], blk - a.block_begin[dir], a.W, a.H, kBlock / HL);
-    uint8_t *out = a.out[dir];
+        if (k < ndirs && blk >= uniform(a.block_begin[k])) dir = k;
+    LineArgs la;
+    la.cl = uniform((const uint32_t *)a.census_l);
+    la.cr = uniform((const uint32_t *)a.census_r);
+    la.out = uniform(a.out[dir]);
+    la.W = uniform(a.W); la.H = uniform(a.H); la.D = uniform(a.D);
+    la.p1 = uniform(a.p1); la.p2 = uniform(a.p2); la.bits = uniform(a.bits);
+    const BlockGeom g = block_geometry(uniform(a.dx[dir]), uniform(a.dy[dir]), blk - uniform(a.block_begin[dir]),
+                                       la.W, la.H, kBlock / HL);
     if (g.kind == 0) {
         // horizontal lines are the longest dependency chains of the pass: more
         // lanes per line to shorten each step, and issue priority
         __builtin_amdgcn_s_setprio(2);
-        run_lines<kDpad / HL, HL, WIDE, true, agg_tile_dwords<DPL, WIDE>()>(a, g, out, tile);
+        run_lines<kDpad / HL, HL, WIDE, true, agg_tile_dwords<DPL, WIDE>()>(la, g, tile);
         __builtin_amdgcn_s_setprio(0);
     } else {
-        run_lines<DPL, kLanesPerLine, WIDE, false, agg_tile_dwords<DPL, WIDE>()>(a, g, out, tile);
+        run_lines<DPL, kLanesPerLine, WIDE, false, agg_tile_dwords<DPL, WIDE>()>(la, g, tile);
     }
 }
 
@@ -485,18 +524,20 @@ __global__ __launch_bounds__(kBlock) void aggregate_kernel(AggregateArgs a)
 // Persistent form for batches: a grid sized to the machine takes work items
 // (pair slot << 20 | block) from a queue in order (longest first) until it is
 // empty; every block leaves once the shared counter passes the item count.
+// (4 waves per SIMD: the compiler keeps the 32-bit-census form within 128
+// VGPRs, so four blocks fit on a CU)
 template <int DPL, bool WIDE, int HL>
-__global__ __launch_bounds__(kBlock) void aggregate_queue_kernel(AggregateQueue q)
+__global__ __launch_bounds__(kBlock, 4) void aggregate_queue_kernel(AggregateQueue q)
 {
     __shared__ uint32_t tile[3][agg_tile_dwords<DPL, WIDE>()];
     __shared__ int cur;
     for (;;) {
         if (threadIdx.x == 0) cur = (int)atomicAdd(q.counter, 1u);
         __syncthreads();
-        const int i = cur;
+        const int i = __builtin_amdgcn_readfirstlane(cur);
         __syncthreads();
         if (i >= q.nitems) break;
-        const uint32_t it = q.items[i];
+        const uint32_t it = __builtin_amdgcn_readfirstlane(q.items[i]);
         aggregate_block<DPL, WIDE, HL>(q.slots[it >> 20], (int)(it & 0xFFFFFu), tile);
     }
 }

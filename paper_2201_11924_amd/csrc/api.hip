@@ -49,11 +49,13 @@ static int validate(const simsense_params *p)
     if (p->median != 0 && p->median != 3) return SIMSENSE_ERR_INVALID_ARGUMENT;
     if (p->subpixel != 0 && p->subpixel != 1) return SIMSENSE_ERR_INVALID_ARGUMENT;
     if (!(p->focal_px == p->focal_px) || !(p->baseline_m == p->baseline_m)) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    if (p->lr_mode != 0 && p->lr_mode != 1) return SIMSENSE_ERR_INVALID_ARGUMENT;
     return SIMSENSE_OK;
 }
 
 struct Layout {
     size_t census, paths, per_px[7], total;
+    bool right_run;  // lr_mode 1: two more census maps and a second per-pixel set
 };
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -66,10 +68,12 @@ static Layout layout(const simsense_params *p)
     l.census = align256(npx * (wide ? 8 : 4));
     l.paths = align256((npx + 1) * padded_disp(p->max_disp));  // + one spare pixel for idle lanes
     static const int px_bytes[7] = {1, 2, 2, 1, 4, 4, 1};  // dint, S1, S2, dright, dsub, masked, flags
-    l.total = 2 * l.census + (size_t)p->num_paths * l.paths;
+    l.right_run = p->lr_mode == 1;
+    const int sets = l.right_run ? 2 : 1;
+    l.total = 2 * sets * l.census + (size_t)p->num_paths * l.paths;
     for (int i = 0; i < 7; ++i) {
         l.per_px[i] = align256(npx * px_bytes[i]);
-        l.total += l.per_px[i];
+        l.total += sets * l.per_px[i];
     }
     return l;
 }
@@ -156,6 +160,33 @@ static AggregateArgs handle_aggregate_args(const simsense_handle *h)
     return ag;
 }
 
+// The right-referenced run is the left-referenced pass on x-flipped census maps
+// with the roles swapped (the right image's map as the reference); the set of
+// path directions is closed under the flip, so only the census inputs change.
+static AggregateArgs right_run_args(AggregateArgs ag, const simsense_handle *h)
+{
+    ag.census_l = h->census_ml;
+    ag.census_r = h->census_mr;
+    return ag;
+}
+
+static int launch_aggregation(simsense_handle *h, const AggregateArgs &ag, AggregateArgs *d_args, hipStream_t s)
+{
+    if (h->tuning.blocks_per_cu > 0) {
+        AggregateQueue q{};
+        q.slots = d_args;
+        q.items = h->d_items;
+        q.nitems = h->nitems;
+        q.counter = h->d_counter;
+        const int grid = std::min(h->nitems, h->tuning.blocks_per_cu * h->num_cus);
+        SS_TRY(launch_zero_counters(h->d_counter, 1, s));
+        SS_TRY(launch_aggregate_queue(q, h->Dpad, h->wide, h->hlanes, grid, s));
+    } else {
+        SS_TRY(launch_aggregate(ag, h->wide, h->hlanes, s));
+    }
+    return SIMSENSE_OK;
+}
+
 // Applies a tuning: lane count, and for the persistent form the work list of
 // line blocks sorted longest first (stable, so equal lengths keep direction order).
 static int apply_tuning(simsense_handle *h, const simsense_batch_tuning &t)
@@ -179,6 +210,10 @@ static int apply_tuning(simsense_handle *h, const simsense_batch_tuning &t)
     SS_TRY(hipMalloc(&h->d_items, std::max<size_t>(items.size(), 1) * sizeof(uint32_t)));
     if (!items.empty()) SS_TRY(hipMemcpy(h->d_items, items.data(), items.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
     SS_TRY(hipMemcpy(h->d_args, &ag, sizeof(ag), hipMemcpyHostToDevice));
+    if (h->p.lr_mode == 1) {
+        const AggregateArgs am = right_run_args(ag, h);
+        SS_TRY(hipMemcpy(h->d_args_m, &am, sizeof(am), hipMemcpyHostToDevice));
+    }
     return SIMSENSE_OK;
 }
 
@@ -192,6 +227,9 @@ int enqueue_match(simsense_handle *h, const uint8_t *left, const uint8_t *right,
     SS_TRY(launch_census(right, pitch, W, H, p.census_w, p.census_h, p.census_mode, h->census_r, h->wide, s));
     profile_mark(h, SIMSENSE_PASS_CENSUS, true, s);
 
+    const AggregateArgs ag = handle_aggregate_args(h);
+    if (h->tuning.blocks_per_cu > 0) SS_TRY(launch_zero_counters(h->d_counter, 1, s));
+    profile_mark(h, SIMSENSE_PASS_AGGREGATE, false, s);
     if (h->tuning.blocks_per_cu > 0) {
         AggregateQueue q{};
         q.slots = h->d_args;
@@ -199,16 +237,11 @@ int enqueue_match(simsense_handle *h, const uint8_t *left, const uint8_t *right,
         q.nitems = h->nitems;
         q.counter = h->d_counter;
         const int grid = std::min(h->nitems, h->tuning.blocks_per_cu * h->num_cus);
-        SS_TRY(launch_zero_counters(h->d_counter, 1, s));
-        profile_mark(h, SIMSENSE_PASS_AGGREGATE, false, s);
         SS_TRY(launch_aggregate_queue(q, h->Dpad, h->wide, h->hlanes, grid, s));
-        profile_mark(h, SIMSENSE_PASS_AGGREGATE, true, s);
     } else {
-        const AggregateArgs ag = handle_aggregate_args(h);
-        profile_mark(h, SIMSENSE_PASS_AGGREGATE, false, s);
         SS_TRY(launch_aggregate(ag, h->wide, h->hlanes, s));
-        profile_mark(h, SIMSENSE_PASS_AGGREGATE, true, s);
     }
+    profile_mark(h, SIMSENSE_PASS_AGGREGATE, true, s);
 
     SelectArgs sa{};
     for (int r = 0; r < h->ndirs; ++r) sa.paths[r] = h->paths[r];
@@ -220,6 +253,25 @@ int enqueue_match(simsense_handle *h, const uint8_t *left, const uint8_t *right,
     sa.disp_right = h->disp_right; sa.disp_sub = h->disp_sub; sa.masked = h->masked; sa.flags = h->flags_pre;
     profile_mark(h, SIMSENSE_PASS_SELECT, false, s);
     SS_TRY(launch_select(sa, s));
+    if (p.lr_mode == 1) {
+        // full right-referenced run into the second per-pixel set, then the check
+        SS_TRY(launch_flip_census(h->census_r, h->census_ml, W, H, h->wide, s));
+        SS_TRY(launch_flip_census(h->census_l, h->census_mr, W, H, h->wide, s));
+        const int rc = launch_aggregation(h, right_run_args(ag, h), h->d_args_m, s);
+        if (rc != SIMSENSE_OK) return rc;
+        SelectArgs sm = sa;
+        sm.uniqueness_pct = 0;
+        sm.lr_max_diff = -1;
+        sm.disp_int = h->disp_int_m; sm.cost_best = h->cost_best_m; sm.cost_second = h->cost_second_m;
+        sm.disp_right = h->disp_right_m; sm.disp_sub = h->disp_sub_m; sm.masked = h->masked_m;
+        sm.flags = h->flags_m;
+        SS_TRY(launch_select(sm, s));
+        LRFullArgs lf{};
+        lf.dint = h->disp_int; lf.dint_m = h->disp_int_m; lf.disp_sub = h->disp_sub;
+        lf.flags = h->flags_pre; lf.masked = h->masked; lf.disp_right = h->disp_right;
+        lf.W = W; lf.H = H; lf.lr = p.lr_max_diff;
+        SS_TRY(launch_lr_full(lf, s));
+    }
     profile_mark(h, SIMSENSE_PASS_SELECT, true, s);
     return SIMSENSE_OK;
 }
@@ -284,13 +336,14 @@ int simsense_create(const simsense_params *params, simsense_handle **out)
         h->num_cus = 256;
     }
     if (hipMalloc(&h->block, l.total) != hipSuccess || hipMalloc(&h->d_counter, 256) != hipSuccess ||
-        hipMalloc(&h->d_args, sizeof(AggregateArgs)) != hipSuccess) {
+        hipMalloc(&h->d_args, 2 * sizeof(AggregateArgs)) != hipSuccess) {
         (void)hipGetLastError();
         (void)hipFree(h->block);
         (void)hipFree(h->d_counter);
         delete h;
         return SIMSENSE_ERR_OUT_OF_MEMORY;
     }
+    h->d_args_m = h->d_args + 1;
     uint8_t *cur = (uint8_t *)h->block;
     h->census_l = cur; cur += l.census;
     h->census_r = cur; cur += l.census;
@@ -302,6 +355,17 @@ int simsense_create(const simsense_params *params, simsense_handle **out)
     h->disp_sub = (float *)cur; cur += l.per_px[4];
     h->masked = (float *)cur; cur += l.per_px[5];
     h->flags_pre = cur; cur += l.per_px[6];
+    if (l.right_run) {
+        h->census_ml = cur; cur += l.census;
+        h->census_mr = cur; cur += l.census;
+        h->disp_int_m = cur; cur += l.per_px[0];
+        h->cost_best_m = (uint16_t *)cur; cur += l.per_px[1];
+        h->cost_second_m = (uint16_t *)cur; cur += l.per_px[2];
+        h->disp_right_m = cur; cur += l.per_px[3];
+        h->disp_sub_m = (float *)cur; cur += l.per_px[4];
+        h->masked_m = (float *)cur; cur += l.per_px[5];
+        h->flags_m = cur; cur += l.per_px[6];
+    }
     h->last_stream = nullptr;
     h->profiling = false;
     h->prof_events = nullptr;

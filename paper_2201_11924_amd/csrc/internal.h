@@ -84,6 +84,20 @@ hipError_t launch_zero_counters(unsigned *c, int n, hipStream_t s);
 hipError_t launch_aggregate_queue(const AggregateQueue &q, int dpad, bool wide, int hl, int grid, hipStream_t s);
 hipError_t launch_select(const SelectArgs &a, hipStream_t s);
 hipError_t launch_post(const PostArgs &a, hipStream_t s);
+// x-flip of a census map (words of 4 or 8 bytes)
+hipError_t launch_flip_census(const void *src, void *dst, int W, int H, bool wide, hipStream_t s);
+// LR check against a full right-referenced run whose winners are given in
+// x-flipped order (dint_m[y][W-1-xr] = dR(xr)): rewrites flag bit 1 and the
+// masked disparity, and writes the right disparities
+struct LRFullArgs {
+    const uint8_t *dint, *dint_m;
+    const float *disp_sub;
+    uint8_t *flags;      // in: bits 0 and 2 of the left selection; out: bit 1 rewritten
+    float *masked;
+    uint8_t *disp_right;
+    int W, H, lr;
+};
+hipError_t launch_lr_full(const LRFullArgs &a, hipStream_t s);
 
 // batched forms: per-slot arguments in device memory, one block per item
 // (slot << 20 | index), items in device memory
@@ -143,6 +157,13 @@ struct simsense_handle {  // opaque to callers
     uint32_t *d_items;
     unsigned *d_counter;
     ss::AggregateArgs *d_args;
+    // full right-referenced run (lr_mode 1): x-flipped census maps (the right
+    // image's as the reference), that run's per-pixel results and its arguments
+    void *census_ml, *census_mr;
+    uint8_t *disp_int_m, *disp_right_m, *flags_m;
+    uint16_t *cost_best_m, *cost_second_m;
+    float *disp_sub_m, *masked_m;
+    ss::AggregateArgs *d_args_m;
     void *block;
     void *census_l, *census_r;
     uint8_t *paths[8];

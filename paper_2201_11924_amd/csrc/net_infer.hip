@@ -56,7 +56,7 @@ constexpr int kW1Row = kpad(8) / 8 + 1, kW4Row = kpad(32) / 8 + 1;  // uint4 per
 
 struct Smem {
     uint4 feat[3][kRowPx];          // 8 bf16 feature channels per pixel
-    uint4 act[3][3][kRowPx][4];     // [layer][ring slot][pixel][32 bf16 channels]
+    uint4 act[3][3][kRowPx][4];     // [layer][ring slot][pixel][32 bf16 channels, chunks swizzled]
     uint4 w1[32][kW1Row];
     uint4 w4[16][kW4Row];
     float4 bias[3][8];              // layers 1..3, 32 channels each
@@ -65,6 +65,11 @@ struct Smem {
 };
 
 __device__ __forceinline__ int slot_of(int j) { return (j + 6) % 3; }  // rows j >= -6
+
+// A pixel's 32 channels are four 16-byte chunks; chunk c of ring pixel p is
+// stored at position c ^ ((p >> 2) & 3), so that the 16 lanes reading one
+// chunk of 16 consecutive pixels (64 bytes apart) hit 16 different 4-bank groups.
+__device__ __forceinline__ int swz(int p, int c) { return c ^ ((p >> 2) & 3); }
 
 // One 32-channel ReLU layer row: 6 tiles x 2 output-channel blocks = 12 units,
 // three per wave (units 3w .. 3w+2, unit u = tile u/2, channel block u%2); a
@@ -93,8 +98,9 @@ __device__ __forceinline__ void layer_row(Smem &sm, const bf16x8 (&wa)[2][9], in
         } else {
             // k = 32c + 8 quad .. +7 -> tap c, channels 8 quad .. +7
             const int slot = slot_of(j - 1 + c / 3), dx = c % 3 - 1;
-            va = sm.act[in_layer][slot][16 * ta + col + dx + 1][quad];
-            vb = sm.act[in_layer][slot][16 * tb + col + dx + 1][quad];
+            const int pa = 16 * ta + col + dx + 1, pb = 16 * tb + col + dx + 1;
+            va = sm.act[in_layer][slot][pa][swz(pa, quad)];
+            vb = sm.act[in_layer][slot][pb][swz(pb, quad)];
         }
     };
     floatx4 acc[3];
@@ -134,7 +140,8 @@ __device__ __forceinline__ void layer_row(Smem &sm, const bf16x8 (&wa)[2][9], in
         uint2 w;
         w.x = pack_bf16(v[0], v[1]);
         w.y = pack_bf16(v[2], v[3]);
-        uint2 *dst = (uint2 *)&sm.act[out_layer][slot][q + 1][0] + (16 * mb + 4 * quad) / 4;
+        // channels 16 mb + 4 quad .. +3: chunk 2 mb + quad / 2, half quad % 2
+        uint2 *dst = (uint2 *)&sm.act[out_layer][slot][q + 1][0] + 2 * swz(q + 1, 2 * mb + quad / 2) + (quad & 1);
         *dst = w;
     }
 }
@@ -296,8 +303,10 @@ __global__ __launch_bounds__(256, 2) void net_infer_kernel(InferArgs a)
                 if (t >= kOutTiles) break;
                 uint4 bv[9];
 #pragma unroll
-                for (int c = 0; c < 9; ++c)
-                    bv[c] = sm.act[2][slot_of(j4 - 1 + c / 3)][kHalo + 16 * t + col + c % 3][quad];
+                for (int c = 0; c < 9; ++c) {
+                    const int pc = kHalo + 16 * t + col + c % 3;
+                    bv[c] = sm.act[2][slot_of(j4 - 1 + c / 3)][pc][swz(pc, quad)];
+                }
                 floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int c = 0; c < 9; ++c)

@@ -450,3 +450,46 @@ hipError_t launch_volume_sum(const PathSet &paths, int ndirs, int W, int H, int 
 }
 
 }  // namespace ss
+
+namespace ss {
+
+// ---------------------------------------------------------------- full right-referenced LR
+namespace {
+template <typename T>
+__global__ __launch_bounds__(256) void flip_census_kernel(const T *__restrict__ src, T *__restrict__ dst, int W, int H)
+{
+    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+    if (x < W) dst[(size_t)y * W + x] = src[(size_t)y * W + (W - 1 - x)];
+}
+
+__global__ __launch_bounds__(256) void lr_full_kernel(LRFullArgs a)
+{
+    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+    if (x >= a.W) return;
+    const size_t row = (size_t)y * a.W, p = row + x;
+    const int d = a.dint[p], xr = x - d;
+    bool lr_ok = true;
+    if (a.lr >= 0) lr_ok = xr >= 0 && abs(d - (int)a.dint_m[row + (a.W - 1 - max(xr, 0))]) <= a.lr;
+    const uint8_t f = (uint8_t)((a.flags[p] & ~2u) | (lr_ok ? 2u : 0u));
+    a.flags[p] = f;
+    a.masked[p] = (f & 7u) == 7u ? a.disp_sub[p] : 0.0f;
+    a.disp_right[p] = a.dint_m[row + (a.W - 1 - x)];
+}
+}  // namespace
+
+hipError_t launch_flip_census(const void *src, void *dst, int W, int H, bool wide, hipStream_t s)
+{
+    dim3 grid((W + 255) / 256, H), block(256);
+    if (wide) hipLaunchKernelGGL(flip_census_kernel<uint64_t>, grid, block, 0, s, (const uint64_t *)src, (uint64_t *)dst, W, H);
+    else hipLaunchKernelGGL(flip_census_kernel<uint32_t>, grid, block, 0, s, (const uint32_t *)src, (uint32_t *)dst, W, H);
+    return hipGetLastError();
+}
+
+hipError_t launch_lr_full(const LRFullArgs &a, hipStream_t s)
+{
+    dim3 grid((a.W + 255) / 256, a.H), block(256);
+    hipLaunchKernelGGL(lr_full_kernel, grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace ss

@@ -32,7 +32,7 @@ PARAM_FIELDS = ("width", "height", "max_disp", "census_w", "census_h", "census_m
 
 class Params(ct.Structure):
     _fields_ = [("struct_size", ct.c_uint32)] + [(n, ct.c_int32) for n in PARAM_FIELDS] + [
-        ("focal_px", ct.c_float), ("baseline_m", ct.c_float)]
+        ("focal_px", ct.c_float), ("baseline_m", ct.c_float), ("lr_mode", ct.c_int32)]
 
     @classmethod
     def from_dict(cls, d: Dict) -> "Params":
@@ -42,6 +42,7 @@ class Params(ct.Structure):
             setattr(p, n, int(d[n]))
         p.focal_px = float(d["focal_px"])
         p.baseline_m = float(d["baseline_m"])
+        p.lr_mode = int(d.get("lr_mode", 0))
         return p
 
 

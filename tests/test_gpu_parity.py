@@ -179,3 +179,24 @@ def test_every_launch_shape_matches_oracle(orc, nat, W, H, D, paths):
         with pytest.raises(nat.SimSenseError):
             ss.set_tuning(*bad)
     ss.close()
+
+
+@pytest.mark.parametrize("W,H,D,paths,kw", [
+    (173, 61, 64, 8, {}), (90, 37, 96, 4, {}), (64, 33, 128, 2, dict(lr_max_diff=0)),
+    (47, 52, 24, 8, dict(census_mode=1, p2=60)), (1, 20, 3, 8, {}), (40, 1, 8, 8, {}),
+])
+def test_full_right_reference_lr_matches_oracle(orc, nat, W, H, D, paths, kw):
+    """lr_mode 1 (a full right-referenced SGM run for the LR check) against the
+    oracle's direct right-referenced computation, for both launch forms."""
+    spec = PairSpec(W, H, planes=3, dmin=0, dmax=max(0.0, min(D - 1, W - 1) * 0.8), noise="gauss", sigma=3.0)
+    left, right = noisy_pair(orc, spec, 3 * W + 5 * H + D)
+    params = params_for(W, H, D, num_paths=paths, lr_mode=1, **kw)
+    ref, g = compare(orc, nat, params, left, right, label=f"lr_mode=1 {kw}")
+    import torch
+    ss = nat.SimSense(params)
+    ss.set_tuning(0, 0)
+    out = ss.compute_all(dev(left), dev(right))
+    torch.cuda.synchronize()
+    assert np.array_equal(host(out["disp_right"]), ref.dright.astype(np.uint8))
+    assert np.array_equal(host(out["flags"]), ref.flags)
+    ss.close()

@@ -319,3 +319,45 @@ def test_end_to_end_constant_shift(orc):
     assert (r.flags[inner] & 3 == 3).all()
     m = r.disp > 0
     assert np.allclose(r.depth[m], 400.0 * np.float64(np.float32(0.055)) / r.disp[m], rtol=1e-6)
+
+
+# ----------------------------------------------------------------- full right-referenced run
+def test_right_reference_mirror_identity(orc):
+    """Matching the right image against the left is left-referenced matching of
+    the x-flipped census maps with the roles swapped: the path set is closed
+    under the flip, so the right-referenced cost, aggregate and winner equal the
+    flipped left-referenced ones computed by the independent left-side functions."""
+    rng = np.random.default_rng(11)
+    H, W, D, bits = 9, 23, 7, 31
+    cl = rng.integers(0, 2 ** 31, (H, W)).astype(np.uint64)
+    cr = rng.integers(0, 2 ** 31, (H, W)).astype(np.uint64)
+    CR = orc.cost_right(cl, cr, D, bits)
+    CM = orc.cost(cr[:, ::-1], cl[:, ::-1], D, bits)
+    assert np.array_equal(CR, CM[:, ::-1])
+    for paths in (2, 4, 8):
+        SM = orc.aggregate(CM, paths, 7, 40)
+        dm = SM.argmin(axis=2)[:, ::-1]  # numpy argmin takes the lowest index on ties
+        assert np.array_equal(orc.right_disp_full(cl, cr, D, bits, paths, 7, 40), dm)
+
+
+def test_right_reference_constant_shift(orc):
+    """right(x) = left(x + d0): the right-referenced run recovers d0 wherever
+    x + d0 and the census window stay inside the image, and the full-run LR
+    check then keeps every interior pixel of the left result."""
+    W, H, D, d0 = 96, 40, 32, 9
+    left, right = make_shift_pair(W, H, d0, seed=21)
+    cl, cr = orc.census(left), orc.census(right)
+    dR = orc.right_disp_full(cl, cr, D, 31, 8, 7, 86)
+    rw = 3
+    assert (dR[:, rw: W - d0 - rw] == d0).all()
+    params = dict(width=W, height=H, max_disp=D, census_w=7, census_h=9, census_mode=0, p1=7, p2=86,
+                  uniqueness_pct=10, lr_max_diff=1, num_paths=8, median=3, subpixel=1,
+                  focal_px=400.0, baseline_m=0.055, lr_mode=1)
+    r = orc.sgm(params, left, right)
+    assert np.array_equal(r.dright, dR)
+    inner = (slice(None), slice(d0 + rw, W - rw))
+    assert (r.dint[inner] == d0).all() and (r.flags[inner] & 3 == 3).all()
+    # the lr_mode only changes the right disparity and what depends on it
+    r0 = orc.sgm(dict(params, lr_mode=0), left, right)
+    assert np.array_equal(r0.dint, r.dint) and np.array_equal(r0.dsub, r.dsub)
+    assert np.array_equal(r0.flags & 5, r.flags & 5)
