@@ -47,7 +47,8 @@ class OrcParams(ct.Structure):
     _fields_ = [(n, ct.c_int32) for n in (
         "width", "height", "max_disp", "census_w", "census_h", "census_mode", "p1", "p2",
         "uniqueness_pct", "lr_max_diff", "num_paths", "median", "subpixel")] + [
-        ("focal_px", ct.c_float), ("baseline_m", ct.c_float), ("lr_mode", ct.c_int32)]
+        ("focal_px", ct.c_float), ("baseline_m", ct.c_float), ("lr_mode", ct.c_int32),
+        ("block_w", ct.c_int32), ("block_h", ct.c_int32)]
 
 
 class OrcResult(ct.Structure):
@@ -89,13 +90,13 @@ def cost(cl: np.ndarray, cr: np.ndarray, D: int, bits: int) -> np.ndarray:
     cl = np.ascontiguousarray(cl, np.uint64)
     cr = np.ascontiguousarray(cr, np.uint64)
     H, W = cl.shape
-    C = np.empty((H, W, D), np.uint8)
+    C = np.empty((H, W, D), np.uint16)
     lib().orc_cost(_p(cl), _p(cr), W, H, D, bits, _p(C))
     return C
 
 
 def path(C: np.ndarray, dx: int, dy: int, p1: int, p2: int) -> np.ndarray:
-    C = np.ascontiguousarray(C, np.uint8)
+    C = np.ascontiguousarray(C, np.uint16)
     H, W, D = C.shape
     L = np.empty((H, W, D), np.uint16)
     lib().orc_path(_p(C), W, H, D, dx, dy, p1, p2, _p(L))
@@ -112,7 +113,7 @@ def path_dirs(num_paths: int):
 
 
 def aggregate(C: np.ndarray, num_paths: int, p1: int, p2: int) -> np.ndarray:
-    C = np.ascontiguousarray(C, np.uint8)
+    C = np.ascontiguousarray(C, np.uint16)
     H, W, D = C.shape
     S = np.empty((H, W, D), np.uint32)
     lib().orc_aggregate(_p(C), W, H, D, num_paths, p1, p2, _p(S))
@@ -143,17 +144,26 @@ def cost_right(cl: np.ndarray, cr: np.ndarray, D: int, bits: int) -> np.ndarray:
     cl = np.ascontiguousarray(cl, np.uint64)
     cr = np.ascontiguousarray(cr, np.uint64)
     H, W = cl.shape
-    C = np.empty((H, W, D), np.uint8)
+    C = np.empty((H, W, D), np.uint16)
     lib().orc_cost_right(_p(cl), _p(cr), W, H, D, bits, _p(C))
     return C
 
 
-def right_disp_full(cl: np.ndarray, cr: np.ndarray, D: int, bits: int, num_paths: int, p1: int, p2: int):
+def block_cost(C: np.ndarray, bw: int, bh: int) -> np.ndarray:
+    C = np.ascontiguousarray(C, np.uint16)
+    H, W, D = C.shape
+    CB = np.empty((H, W, D), np.uint16)
+    lib().orc_block_cost(_p(C), W, H, D, bw, bh, _p(CB))
+    return CB
+
+
+def right_disp_full(cl: np.ndarray, cr: np.ndarray, D: int, bits: int, num_paths: int, p1: int, p2: int,
+                    bw: int = 1, bh: int = 1):
     cl = np.ascontiguousarray(cl, np.uint64)
     cr = np.ascontiguousarray(cr, np.uint64)
     H, W = cl.shape
     dR = np.empty((H, W), np.int32)
-    lib().orc_right_disp_full(_p(cl), _p(cr), W, H, D, bits, num_paths, p1, p2, _p(dR))
+    lib().orc_right_disp_full(_p(cl), _p(cr), W, H, D, bits, num_paths, p1, p2, bw, bh, _p(dR))
     return dR
 
 
@@ -204,7 +214,8 @@ def sgm(params: dict, left: np.ndarray, right: np.ndarray, keep_volume: bool = F
     H, W = left.shape
     assert params["width"] == W and params["height"] == H
     D = params["max_disp"]
-    pp = OrcParams(**{k: params.get(k, 0) if k == "lr_mode" else params[k] for k, _ in OrcParams._fields_})
+    optional = {"lr_mode": 0, "block_w": 1, "block_h": 1}
+    pp = OrcParams(**{k: params.get(k, optional[k]) if k in optional else params[k] for k, _ in OrcParams._fields_})
     arrs = dict(census_l=np.empty((H, W), np.uint64), census_r=np.empty((H, W), np.uint64),
                 S=np.empty((H, W, D), np.uint32) if keep_volume else None,
                 dint=np.empty((H, W), np.int32), s1=np.empty((H, W), np.int32),

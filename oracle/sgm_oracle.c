@@ -18,7 +18,8 @@
  *    center-symmetric mode: for every o before the centre in raster order,
  *    bit = [I(p+o) > I(p-o)]; samples outside the image clamp to the edge.
  *  - cost C(x,y,d) = popcount(cL(x,y) ^ cR(x-d,y)), and the number of census
- *    bits where x-d < 0; disparities 0..D-1.
+ *    bits where x-d < 0; disparities 0..D-1; for block matching (SGBM) the
+ *    pixel costs summed over a block with clamped samples.
  *  - path recurrence in its normalised form, first pixel of a path L = C.
  *  - winner: lowest d on ties; uniqueness second best over |d-d*| >= 2,
  *    valid iff 100*S1 <= (100-u)*S2; sub-pixel parabola through d*-1, d*, d*+1;
@@ -97,14 +98,14 @@ void orc_census(const uint8_t *img, int W, int H, int pitch, int cw, int ch, int
 int orc_popcount(uint64_t v) { return __builtin_popcountll(v); }
 
 /* Hamming matching cost, C[(y*W + x)*D + d]. */
-void orc_cost(const uint64_t *cl, const uint64_t *cr, int W, int H, int D, int bits, uint8_t *C)
+void orc_cost(const uint64_t *cl, const uint64_t *cr, int W, int H, int D, int bits, uint16_t *C)
 {
     for (int y = 0; y < H; ++y)
         for (int x = 0; x < W; ++x)
             for (int d = 0; d < D; ++d) {
                 int c = bits;
                 if (x - d >= 0) c = orc_popcount(cl[(size_t)y * W + x] ^ cr[(size_t)y * W + x - d]);
-                C[((size_t)y * W + x) * D + d] = (uint8_t)c;
+                C[((size_t)y * W + x) * D + d] = (uint16_t)c;
             }
 }
 
@@ -113,7 +114,7 @@ void orc_cost(const uint64_t *cl, const uint64_t *cr, int W, int H, int D, int b
  *   L(p,d) = C(p,d) + min(L(p-r,d), L(p-r,d-1)+P1, L(p-r,d+1)+P1, m(p-r)+P2) - m(p-r),
  *   m(q) = min_k L(q,k);  L(p,d) = C(p,d) where p-r lies outside the image.
  * Pixels are visited so that p-r is always finished before p. */
-void orc_path(const uint8_t *C, int W, int H, int D, int dx, int dy, int P1, int P2, uint16_t *L)
+void orc_path(const uint16_t *C, int W, int H, int D, int dx, int dy, int P1, int P2, uint16_t *L)
 {
     int y0 = dy >= 0 ? 0 : H - 1, y1 = dy >= 0 ? H : -1, ys = dy >= 0 ? 1 : -1;
     int x0 = dx >= 0 ? 0 : W - 1, x1 = dx >= 0 ? W : -1, xs = dx >= 0 ? 1 : -1;
@@ -152,7 +153,7 @@ void orc_path_dir(int i, int *dx, int *dy)
 }
 
 /* S(p,d) = sum over the chosen paths of L_r(p,d). */
-void orc_aggregate(const uint8_t *C, int W, int H, int D, int num_paths, int P1, int P2, uint32_t *S)
+void orc_aggregate(const uint16_t *C, int W, int H, int D, int num_paths, int P1, int P2, uint32_t *S)
 {
     size_t n = (size_t)W * H * D;
     uint16_t *L = (uint16_t *)malloc(n * sizeof(uint16_t));
@@ -216,27 +217,53 @@ void orc_right_disp(const uint32_t *S, int W, int H, int D, int32_t *dR)
 /* Right-referenced matching cost: the right pixel xr against the left pixel
  * xr + d, CR[(y*W + xr)*D + d] = popcount(cR(xr,y) ^ cL(xr+d,y)), and the number
  * of census bits where xr + d > W-1. */
-void orc_cost_right(const uint64_t *cl, const uint64_t *cr, int W, int H, int D, int bits, uint8_t *CR)
+void orc_cost_right(const uint64_t *cl, const uint64_t *cr, int W, int H, int D, int bits, uint16_t *CR)
 {
     for (int y = 0; y < H; ++y)
         for (int xr = 0; xr < W; ++xr)
             for (int d = 0; d < D; ++d) {
                 int c = bits;
                 if (xr + d <= W - 1) c = orc_popcount(cr[(size_t)y * W + xr] ^ cl[(size_t)y * W + xr + d]);
-                CR[((size_t)y * W + xr) * D + d] = (uint8_t)c;
+                CR[((size_t)y * W + xr) * D + d] = (uint16_t)c;
+            }
+}
+
+/* Semi-global block matching cost (Sec. VI-D: the Hamming distance between the
+ * local regions of the two pixels): the pixel costs summed over a bw x bh block
+ * centred on the pixel, block samples outside the image clamped to the edge,
+ *   CB(x,y,d) = sum_{|u|<=bw/2, |v|<=bh/2} C(clamp(x+u), clamp(y+v), d). */
+void orc_block_cost(const uint16_t *C, int W, int H, int D, int bw, int bh, uint16_t *CB)
+{
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x)
+            for (int d = 0; d < D; ++d) {
+                int sum = 0;
+                for (int v = -(bh / 2); v <= bh / 2; ++v)
+                    for (int u = -(bw / 2); u <= bw / 2; ++u) {
+                        int cx = clampi(x + u, 0, W - 1), cy = clampi(y + v, 0, H - 1);
+                        sum += C[((size_t)cy * W + cx) * D + d];
+                    }
+                CB[((size_t)y * W + x) * D + d] = (uint16_t)sum;
             }
 }
 
 /* Right disparity from a full right-referenced SGM run: the right-referenced
- * cost aggregated over the same paths with the same penalties, then the winner
- * of each right pixel (lowest d on ties). */
+ * cost (block-summed like the left one when bw x bh > 1) aggregated over the
+ * same paths with the same penalties, then the winner of each right pixel
+ * (lowest d on ties). */
 void orc_right_disp_full(const uint64_t *cl, const uint64_t *cr, int W, int H, int D, int bits, int num_paths,
-                         int P1, int P2, int32_t *dR)
+                         int P1, int P2, int bw, int bh, int32_t *dR)
 {
     size_t n = (size_t)W * H * D;
-    uint8_t *CR = (uint8_t *)malloc(n);
+    uint16_t *CR = (uint16_t *)malloc(n * sizeof(uint16_t));
     uint32_t *SR = (uint32_t *)malloc(n * sizeof(uint32_t));
     orc_cost_right(cl, cr, W, H, D, bits, CR);
+    if (bw * bh > 1) {
+        uint16_t *CB = (uint16_t *)malloc(n * sizeof(uint16_t));
+        orc_block_cost(CR, W, H, D, bw, bh, CB);
+        memcpy(CR, CB, n * sizeof(uint16_t));
+        free(CB);
+    }
     orc_aggregate(CR, W, H, D, num_paths, P1, P2, SR);
     for (size_t p = 0; p < (size_t)W * H; ++p) {
         int best = 0;
@@ -300,6 +327,7 @@ typedef struct orc_params {
     int32_t p1, p2, uniqueness_pct, lr_max_diff, num_paths, median, subpixel;
     float focal_px, baseline_m;
     int32_t lr_mode; /* 0: right disparity read off the left volume; 1: full right-referenced run */
+    int32_t block_w, block_h; /* matching block; 1 x 1 = SGM, larger = SGBM */
 } orc_params;
 
 typedef struct orc_result {
@@ -316,7 +344,8 @@ int orc_sgm(const orc_params *pp, const uint8_t *left, const uint8_t *right, orc
     int W = pp->width, H = pp->height, D = pp->max_disp;
     size_t npx = (size_t)W * H, nvol = npx * D;
     int bits = orc_census_bits(pp->census_w, pp->census_h, pp->census_mode);
-    uint8_t *C = (uint8_t *)malloc(nvol);
+    uint16_t *C = (uint16_t *)malloc(nvol * sizeof(uint16_t));
+    int bw = pp->block_w > 0 ? pp->block_w : 1, bh = pp->block_h > 0 ? pp->block_h : 1;
     uint32_t *S = r->S ? r->S : (uint32_t *)malloc(nvol * sizeof(uint32_t));
     uint8_t *vu = (uint8_t *)malloc(npx), *vlr = (uint8_t *)malloc(npx);
     double *masked = (double *)malloc(npx * sizeof(double));
@@ -325,10 +354,18 @@ int orc_sgm(const orc_params *pp, const uint8_t *left, const uint8_t *right, orc
     orc_census(left, W, H, W, pp->census_w, pp->census_h, pp->census_mode, r->census_l);
     orc_census(right, W, H, W, pp->census_w, pp->census_h, pp->census_mode, r->census_r);
     orc_cost(r->census_l, r->census_r, W, H, D, bits, C);
+    if (bw * bh > 1) {
+        uint16_t *CB = (uint16_t *)malloc(nvol * sizeof(uint16_t));
+        if (!CB) return -1;
+        orc_block_cost(C, W, H, D, bw, bh, CB);
+        memcpy(C, CB, nvol * sizeof(uint16_t));
+        free(CB);
+    }
     orc_aggregate(C, W, H, D, pp->num_paths, pp->p1, pp->p2, S);
     orc_wta(S, W, H, D, pp->uniqueness_pct, pp->subpixel, r->dint, r->s1, r->s2, vu, r->dsub);
     if (pp->lr_mode == 1)
-        orc_right_disp_full(r->census_l, r->census_r, W, H, D, bits, pp->num_paths, pp->p1, pp->p2, r->dright);
+        orc_right_disp_full(r->census_l, r->census_r, W, H, D, bits, pp->num_paths, pp->p1, pp->p2, bw, bh,
+                            r->dright);
     else
         orc_right_disp(S, W, H, D, r->dright);
     orc_lr_check(r->dint, r->dright, W, H, pp->lr_max_diff, vlr);

@@ -361,3 +361,42 @@ def test_right_reference_constant_shift(orc):
     r0 = orc.sgm(dict(params, lr_mode=0), left, right)
     assert np.array_equal(r0.dint, r.dint) and np.array_equal(r0.dsub, r.dsub)
     assert np.array_equal(r0.flags & 5, r.flags & 5)
+
+
+# ----------------------------------------------------------------- semi-global block matching (SGBM)
+def test_block_cost_is_a_clamped_box_filter(orc):
+    """The block cost equals the box filter of each disparity slice with
+    edge-replicating borders (scipy's uniform_filter, mode='nearest') times the
+    block area; a 1x1 block is the pixel cost; a constant slice scales by the area."""
+    from scipy.ndimage import uniform_filter
+    rng = np.random.default_rng(5)
+    H, W, D = 11, 17, 6
+    C = rng.integers(0, 32, (H, W, D)).astype(np.uint16)
+    assert np.array_equal(orc.block_cost(C, 1, 1), C)
+    for bw, bh in ((3, 3), (5, 3), (3, 7), (1, 5)):
+        want = np.stack([np.rint(uniform_filter(C[:, :, d].astype(np.float64), size=(bh, bw), mode="nearest")
+                                 * (bw * bh)) for d in range(D)], axis=2)
+        assert np.array_equal(orc.block_cost(C, bw, bh), want.astype(np.uint16)), (bw, bh)
+    K = np.full((H, W, D), 7, np.uint16)
+    assert (orc.block_cost(K, 5, 3) == 7 * 15).all()
+
+
+def test_sgbm_constant_shift_and_right_reference(orc):
+    """A noise-free constant shift is recovered exactly by block matching away
+    from the borders; the right-referenced block run obeys the flip identity."""
+    W, H, D, d0 = 96, 40, 32, 9
+    left, right = make_shift_pair(W, H, d0, seed=23)
+    params = dict(width=W, height=H, max_disp=D, census_w=5, census_h=5, census_mode=0, p1=20, p2=120,
+                  uniqueness_pct=10, lr_max_diff=1, num_paths=8, median=3, subpixel=1,
+                  focal_px=400.0, baseline_m=0.055, block_w=3, block_h=3)
+    r = orc.sgm(params, left, right)
+    m = 2 + 1  # census radius + block radius
+    inner = (slice(None), slice(d0 + m, W - m))
+    assert (r.dint[inner] == d0).all()
+    cl, cr = orc.census(left, 5, 5, 0), orc.census(right, 5, 5, 0)
+    bits = orc.census_bits(5, 5, 0)
+    CB = orc.block_cost(orc.cost_right(cl, cr, D, bits), 3, 3)
+    CM = orc.block_cost(orc.cost(cr[:, ::-1], cl[:, ::-1], D, bits), 3, 3)
+    assert np.array_equal(CB, CM[:, ::-1])
+    dm = orc.aggregate(CM, 8, 20, 120).argmin(axis=2)[:, ::-1]
+    assert np.array_equal(orc.right_disp_full(cl, cr, D, bits, 8, 20, 120, 3, 3), dm)
