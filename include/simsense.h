@@ -52,7 +52,8 @@ typedef enum simsense_status {
  *  census_mode      0 = center-symmetric census (the paper's choice, Sec. VI-D;
  *                   (w*h-1)/2 bits), 1 = full census (w*h-1 bits); at most 64 bits.
  *  p1, p2           SGM penalties for a disparity change of 1 and of more than 1;
- *                   0 <= p1 <= p2 and bits + p2 <= 255 (path values are stored in 8 bits).
+ *                   0 <= p1 <= p2 and bits + p2 <= 255 (path values are stored in 8 bits;
+ *                   see block_w for the SGBM bound).
  *  uniqueness_pct   u in 0..99: a pixel is kept only if 100*S1 <= (100-u)*S2, S2 being
  *                   the best aggregated cost at least two disparities away; 0 disables.
  *  lr_max_diff      left-right check tolerance in pixels; negative disables.
@@ -65,6 +66,14 @@ typedef enum simsense_status {
  *                   volume, dR(xr) = argmin_d S(xr+d, d); 1 = a full right-referenced SGM run
  *                   (cost of right pixel xr against left pixel xr+d, the same paths and
  *                   penalties), which doubles the matching work.  Batches support 0 only.
+ *  block_w/_h       matching block, odd, 1..31 each.  1 x 1 is SGM: the cost of a pixel pair
+ *                   is their census Hamming distance.  Larger blocks give semi-global block
+ *                   matching (SGBM, Sec. VI-D: the Hamming distance between the pixels' local
+ *                   regions): the Hamming costs summed over the block centred on the pixel,
+ *                   block samples outside the image clamped to the edge.  SGBM keeps 16-bit
+ *                   path values and requires bits * block_w * block_h + p2 <= 8191; it runs
+ *                   the aggregation with one block per line block (the tuning is not used),
+ *                   and is not available to batches or the learned path.
  */
 typedef struct simsense_params {
     uint32_t struct_size;
@@ -75,6 +84,7 @@ typedef struct simsense_params {
     int32_t num_paths, median, subpixel;
     float focal_px, baseline_m;
     int32_t lr_mode;
+    int32_t block_w, block_h;
 } simsense_params;
 
 /* Bits of the per-pixel flag byte written by the compute calls. */

@@ -185,6 +185,65 @@ __host__ __device__ constexpr int vmcnt_encoding(int n)
     return n > 63 ? vmcnt_encoding(63) : (n & 0xF) | (0x7 << 4) | (0xF << 8) | (((n >> 4) & 0x3) << 14);
 }
 
+// dpl 16-bit values (the low halves of v) to consecutive u16 slots (global)
+template <int DPL>
+__device__ __forceinline__ void store_u16(uint16_t *dst, const uint32_t (&v)[DPL])
+{
+    uint8_t *p = (uint8_t *)dst;
+    if constexpr (DPL == 1) {
+        gstore(p, (uint16_t)v[0]);
+    } else {
+        constexpr int NW = DPL / 2;
+        uint32_t w[NW];
+#pragma unroll
+        for (int i = 0; i < NW; ++i) w[i] = (v[2 * i] & 0xFFFFu) | (v[2 * i + 1] << 16);
+        if constexpr (NW % 4 == 0) {
+#pragma unroll
+            for (int i = 0; i < NW; i += 4) gstore(p + 4 * i, u32x4_t{w[i], w[i + 1], w[i + 2], w[i + 3]});
+        } else if constexpr (NW % 2 == 0) {
+#pragma unroll
+            for (int i = 0; i < NW; i += 2) gstore(p + 4 * i, u32x2_t{w[i], w[i + 1]});
+        } else {
+#pragma unroll
+            for (int i = 0; i < NW; ++i) gstore(p + 4 * i, w[i]);
+        }
+    }
+}
+
+// dpl consecutive 16-bit values, widened to 32 bits
+template <int DPL>
+__device__ __forceinline__ void load_u16(const uint16_t *src, uint32_t (&v)[DPL])
+{
+    if constexpr (DPL == 1) {
+        v[0] = *src;
+    } else {
+        constexpr int NW = DPL / 2;
+        uint32_t w[NW];
+        const uint32_t *p = (const uint32_t *)src;
+        if constexpr (NW % 4 == 0) {
+#pragma unroll
+            for (int i = 0; i < NW; i += 4) {
+                const uint4 q = *(const uint4 *)(p + i);
+                w[i] = q.x; w[i + 1] = q.y; w[i + 2] = q.z; w[i + 3] = q.w;
+            }
+        } else if constexpr (NW % 2 == 0) {
+#pragma unroll
+            for (int i = 0; i < NW; i += 2) {
+                const uint2 q = *(const uint2 *)(p + i);
+                w[i] = q.x; w[i + 1] = q.y;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < NW; ++i) w[i] = p[i];
+        }
+#pragma unroll
+        for (int i = 0; i < NW; ++i) {
+            v[2 * i] = w[i] & 0xFFFFu;
+            v[2 * i + 1] = w[i] >> 16;
+        }
+    }
+}
+
 // global store instructions store_bytes issues per step
 template <int DPL>
 __host__ __device__ constexpr int store_ops()

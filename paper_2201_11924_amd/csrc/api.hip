@@ -43,7 +43,13 @@ static int validate(const simsense_params *p)
     if (p->census_w * p->census_h < 3) return SIMSENSE_ERR_INVALID_ARGUMENT;
     const int bits = census_bits(p->census_w, p->census_h, p->census_mode);
     if (bits > 64 || p->census_w > 65 || p->census_h > 65) return SIMSENSE_ERR_INVALID_ARGUMENT;
-    if (p->p1 < 0 || p->p2 < p->p1 || bits + p->p2 > 255) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    if (p->block_w < 1 || p->block_h < 1 || p->block_w > 31 || p->block_h > 31 || !(p->block_w & 1) ||
+        !(p->block_h & 1))
+        return SIMSENSE_ERR_INVALID_ARGUMENT;
+    const bool block = p->block_w * p->block_h > 1;
+    if (p->p1 < 0 || p->p2 < p->p1) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    if (!block && bits + p->p2 > 255) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    if (block && bits * p->block_w * p->block_h + p->p2 > 8191) return SIMSENSE_ERR_INVALID_ARGUMENT;
     if (p->uniqueness_pct < 0 || p->uniqueness_pct > 99) return SIMSENSE_ERR_INVALID_ARGUMENT;
     if (p->num_paths != 2 && p->num_paths != 4 && p->num_paths != 8) return SIMSENSE_ERR_INVALID_ARGUMENT;
     if (p->median != 0 && p->median != 3) return SIMSENSE_ERR_INVALID_ARGUMENT;
@@ -56,6 +62,7 @@ static int validate(const simsense_params *p)
 struct Layout {
     size_t census, paths, per_px[7], total;
     bool right_run;  // lr_mode 1: two more census maps and a second per-pixel set
+    size_t volume;   // SGBM: the block-cost volume (16-bit, d fastest)
 };
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -66,11 +73,14 @@ static Layout layout(const simsense_params *p)
     const size_t npx = (size_t)p->width * p->height;
     const bool wide = census_bits(p->census_w, p->census_h, p->census_mode) > 32;
     l.census = align256(npx * (wide ? 8 : 4));
-    l.paths = align256((npx + 1) * padded_disp(p->max_disp));  // + one spare pixel for idle lanes
+    const bool block = p->block_w * p->block_h > 1;
+    // + one spare pixel for idle lanes; 16-bit path values for block matching
+    l.paths = align256((npx + 1) * padded_disp(p->max_disp) * (block ? 2 : 1));
+    l.volume = block ? align256(npx * padded_disp(p->max_disp) * 2) : 0;
     static const int px_bytes[7] = {1, 2, 2, 1, 4, 4, 1};  // dint, S1, S2, dright, dsub, masked, flags
     l.right_run = p->lr_mode == 1;
     const int sets = l.right_run ? 2 : 1;
-    l.total = 2 * sets * l.census + (size_t)p->num_paths * l.paths;
+    l.total = 2 * sets * l.census + (size_t)p->num_paths * l.paths + l.volume;
     for (int i = 0; i < 7; ++i) {
         l.per_px[i] = align256(npx * px_bytes[i]);
         l.total += sets * l.per_px[i];
@@ -187,6 +197,31 @@ static int launch_aggregation(simsense_handle *h, const AggregateArgs &ag, Aggre
     return SIMSENSE_OK;
 }
 
+// Block matching (SGBM): block costs of the given census maps into the volume,
+// then the aggregation fed from it into the path buffers (16-bit values).
+static int sgbm_aggregation(simsense_handle *h, const void *cl, const void *cr, hipStream_t s)
+{
+    const simsense_params &p = h->p;
+    BlockCostArgs bc{};
+    bc.census_l = cl; bc.census_r = cr;
+    bc.W = p.width; bc.H = p.height; bc.bits = h->bits; bc.bw = p.block_w; bc.bh = p.block_h;
+    bc.vol = h->volume;
+    SS_TRY(launch_block_cost(bc, h->Dpad, h->wide, s));
+    VolumeArgs va{};
+    va.vol = h->volume;
+    va.W = p.width; va.H = p.height; va.D = p.max_disp; va.Dpad = h->Dpad; va.p1 = p.p1; va.p2 = p.p2;
+    va.ndirs = h->ndirs;
+    va.block_begin[0] = 0;
+    for (int r = 0; r < h->ndirs; ++r) {
+        va.dx[r] = kPathDx[r];
+        va.dy[r] = kPathDy[r];
+        va.out[r] = (uint16_t *)h->paths[r];
+        va.block_begin[r + 1] = va.block_begin[r] + aggregate_blocks(kPathDx[r], kPathDy[r], p.width, p.height, 16);
+    }
+    SS_TRY(launch_aggregate_volume(va, s));
+    return SIMSENSE_OK;
+}
+
 // Applies a tuning: lane count, and for the persistent form the work list of
 // line blocks sorted longest first (stable, so equal lengths keep direction order).
 static int apply_tuning(simsense_handle *h, const simsense_batch_tuning &t)
@@ -217,7 +252,8 @@ static int apply_tuning(simsense_handle *h, const simsense_batch_tuning &t)
     return SIMSENSE_OK;
 }
 
-int enqueue_match(simsense_handle *h, const uint8_t *left, const uint8_t *right, int pitch, hipStream_t s)
+int enqueue_match(simsense_handle *h, const uint8_t *left, const uint8_t *right, int pitch, hipStream_t s,
+                  uint16_t *volume_out)
 {
     const simsense_params &p = h->p;
     const int W = p.width, H = p.height, D = p.max_disp;
@@ -228,9 +264,14 @@ int enqueue_match(simsense_handle *h, const uint8_t *left, const uint8_t *right,
     profile_mark(h, SIMSENSE_PASS_CENSUS, true, s);
 
     const AggregateArgs ag = handle_aggregate_args(h);
-    if (h->tuning.blocks_per_cu > 0) SS_TRY(launch_zero_counters(h->d_counter, 1, s));
+    const bool queue = !h->sgbm && h->tuning.blocks_per_cu > 0;
+    if (queue) SS_TRY(launch_zero_counters(h->d_counter, 1, s));
     profile_mark(h, SIMSENSE_PASS_AGGREGATE, false, s);
-    if (h->tuning.blocks_per_cu > 0) {
+    if (h->sgbm) {
+        // block costs, then the aggregation fed from them
+        const int rc = sgbm_aggregation(h, h->census_l, h->census_r, s);
+        if (rc != SIMSENSE_OK) return rc;
+    } else if (queue) {
         AggregateQueue q{};
         q.slots = h->d_args;
         q.items = h->d_items;
@@ -242,13 +283,21 @@ int enqueue_match(simsense_handle *h, const uint8_t *left, const uint8_t *right,
         SS_TRY(launch_aggregate(ag, h->wide, h->hlanes, s));
     }
     profile_mark(h, SIMSENSE_PASS_AGGREGATE, true, s);
+    if (volume_out) {
+        // the summed volume of this (left-referenced) run, before a right-referenced
+        // run reuses the path buffers
+        PathSet ps{};
+        for (int r = 0; r < h->ndirs; ++r) ps.p[r] = h->paths[r];
+        SS_TRY(launch_volume_sum(ps, h->ndirs, h->sgbm, W, H, D, h->Dpad, volume_out, s));
+    }
 
     SelectArgs sa{};
     for (int r = 0; r < h->ndirs; ++r) sa.paths[r] = h->paths[r];
     sa.ndirs = h->ndirs;
     sa.W = W; sa.H = H; sa.D = D; sa.Dpad = h->Dpad;
     sa.uniqueness_pct = p.uniqueness_pct; sa.lr_max_diff = p.lr_max_diff; sa.subpixel = p.subpixel;
-    sa.small_values = h->bits + p.p2 <= 127;
+    sa.values16 = h->sgbm;
+    sa.small_values = !h->sgbm && h->bits + p.p2 <= 127;
     sa.disp_int = h->disp_int; sa.cost_best = h->cost_best; sa.cost_second = h->cost_second;
     sa.disp_right = h->disp_right; sa.disp_sub = h->disp_sub; sa.masked = h->masked; sa.flags = h->flags_pre;
     profile_mark(h, SIMSENSE_PASS_SELECT, false, s);
@@ -257,7 +306,8 @@ int enqueue_match(simsense_handle *h, const uint8_t *left, const uint8_t *right,
         // full right-referenced run into the second per-pixel set, then the check
         SS_TRY(launch_flip_census(h->census_r, h->census_ml, W, H, h->wide, s));
         SS_TRY(launch_flip_census(h->census_l, h->census_mr, W, H, h->wide, s));
-        const int rc = launch_aggregation(h, right_run_args(ag, h), h->d_args_m, s);
+        const int rc = h->sgbm ? sgbm_aggregation(h, h->census_ml, h->census_mr, s)
+                               : launch_aggregation(h, right_run_args(ag, h), h->d_args_m, s);
         if (rc != SIMSENSE_OK) return rc;
         SelectArgs sm = sa;
         sm.uniqueness_pct = 0;
@@ -331,6 +381,7 @@ int simsense_create(const simsense_params *params, simsense_handle **out)
     h->Dpad = padded_disp(params->max_disp);
     h->hlanes = horizontal_lanes(h->Dpad);
     h->ndirs = params->num_paths;
+    h->sgbm = params->block_w * params->block_h > 1;
     if (hipDeviceGetAttribute(&h->num_cus, hipDeviceAttributeMultiprocessorCount, 0) != hipSuccess) {
         (void)hipGetLastError();
         h->num_cus = 256;
@@ -355,6 +406,10 @@ int simsense_create(const simsense_params *params, simsense_handle **out)
     h->disp_sub = (float *)cur; cur += l.per_px[4];
     h->masked = (float *)cur; cur += l.per_px[5];
     h->flags_pre = cur; cur += l.per_px[6];
+    if (l.volume) {
+        h->volume = (uint16_t *)cur;
+        cur += l.volume;
+    }
     if (l.right_run) {
         h->census_ml = cur; cur += l.census;
         h->census_mr = cur; cur += l.census;
@@ -408,7 +463,7 @@ int simsense_compute_ex(simsense_handle *h, const uint8_t *left, const uint8_t *
     const size_t npx = (size_t)W * H;
     int rc = profile_begin_call(h);
     if (rc != SIMSENSE_OK) return rc;
-    rc = enqueue_match(h, left, right, pitch, s);
+    rc = enqueue_match(h, left, right, pitch, s, o->volume);
     if (rc != SIMSENSE_OK) return rc;
     rc = enqueue_post(h, h->masked, h->flags_pre, o, s);
     if (rc != SIMSENSE_OK) return rc;
@@ -425,16 +480,11 @@ int simsense_compute_ex(simsense_handle *h, const uint8_t *left, const uint8_t *
         SS_TRY(launch_census(left, pitch, W, H, p.census_w, p.census_h, p.census_mode, o->census_left, true, s));
     if (o->census_right)
         SS_TRY(launch_census(right, pitch, W, H, p.census_w, p.census_h, p.census_mode, o->census_right, true, s));
-    if (o->volume) {
-        PathSet ps{};
-        for (int r = 0; r < h->ndirs; ++r) ps.p[r] = h->paths[r];
-        SS_TRY(launch_volume_sum(ps, h->ndirs, W, H, D, h->Dpad, o->volume, s));
-    }
     if (o->features) {
         net::FeatureArgs fa{};
         fa.ir = left; fa.pitch = pitch; fa.W = W;
         fa.s1 = h->cost_best; fa.s2 = h->cost_second; fa.dint = h->disp_int;
-        fa.max_disp = D; fa.smax = (float)(h->ndirs * (h->bits + p.p2));
+        fa.max_disp = D; fa.smax = (float)(h->ndirs * (h->bits * p.block_w * p.block_h + p.p2));
         fa.features = o->features; fa.P = (int64_t)npx;
         SS_TRY(net::launch_features(fa, s));
     }

@@ -425,6 +425,7 @@ int simsense_batch_create(const simsense_params *params, int32_t n, simsense_bat
         const int rc = validate_params(&params[s]);
         if (rc != SIMSENSE_OK) return rc;
         if (params[s].lr_mode != 0) return SIMSENSE_ERR_UNSUPPORTED;  // batches read dR off the left volume
+        if (params[s].block_w * params[s].block_h > 1) return SIMSENSE_ERR_UNSUPPORTED;  // no block matching
         const bool wide = census_bits(params[s].census_w, params[s].census_h, params[s].census_mode) > 32;
         if (s == 0) wide0 = wide;
         else if (wide != wide0) return SIMSENSE_ERR_UNSUPPORTED;  // one census word width per batch

@@ -44,7 +44,8 @@ struct AggregateArgs {
 };
 
 struct SelectArgs {
-    const uint8_t *paths[8];
+    const uint8_t *paths[8];  // 8-bit path values, or 16-bit when values16
+    int values16;
     int ndirs;
     int W, H, D, Dpad;
     int uniqueness_pct, lr_max_diff, subpixel;
@@ -84,6 +85,24 @@ hipError_t launch_zero_counters(unsigned *c, int n, hipStream_t s);
 hipError_t launch_aggregate_queue(const AggregateQueue &q, int dpad, bool wide, int hl, int grid, hipStream_t s);
 hipError_t launch_select(const SelectArgs &a, hipStream_t s);
 hipError_t launch_post(const PostArgs &a, hipStream_t s);
+// Semi-global block matching: the block-cost volume and the aggregation fed
+// from it (16-bit path values, one block per line block).
+struct BlockCostArgs {
+    const void *census_l, *census_r;  // uint32 words, or uint64 when bits > 32
+    int W, H, bits, bw, bh;
+    uint16_t *vol;                    // W*H*Dpad, d fastest
+};
+struct VolumeArgs {
+    const uint16_t *vol;
+    int W, H, D, Dpad, p1, p2;
+    int ndirs;
+    int dx[8], dy[8];
+    int block_begin[9];  // 16-line blocks, prefix sums per direction
+    uint16_t *out[8];    // per-direction path values, (W*H + 1)*Dpad
+};
+hipError_t launch_block_cost(const BlockCostArgs &a, int dpad, bool wide, hipStream_t s);
+hipError_t launch_aggregate_volume(const VolumeArgs &a, hipStream_t s);
+
 // x-flip of a census map (words of 4 or 8 bytes)
 hipError_t launch_flip_census(const void *src, void *dst, int W, int H, bool wide, hipStream_t s);
 // LR check against a full right-referenced run whose winners are given in
@@ -128,7 +147,7 @@ int census_tiles(int W, int H);
 struct PathSet {
     const uint8_t *p[8];
 };
-hipError_t launch_volume_sum(const PathSet &paths, int ndirs, int W, int H, int D, int Dpad,
+hipError_t launch_volume_sum(const PathSet &paths, int ndirs, bool values16, int W, int H, int D, int Dpad,
                              uint16_t *out, hipStream_t s);
 
 // ---------------------------------------------------------------- handle
@@ -136,7 +155,9 @@ hipError_t launch_volume_sum(const PathSet &paths, int ndirs, int W, int H, int 
 //  enqueue_match: census, aggregation and selection into the handle's scratch
 //                 (d*, S1, S2, dR, sub-pixel, masked disparity, flags bits 0..2);
 //  enqueue_post:  median + depth of a masked map into the caller's outputs.
-int enqueue_match(simsense_handle *h, const uint8_t *left, const uint8_t *right, int pitch, hipStream_t s);
+//                 (volume_out, if set, receives the summed path costs S)
+int enqueue_match(simsense_handle *h, const uint8_t *left, const uint8_t *right, int pitch, hipStream_t s,
+                  uint16_t *volume_out = nullptr);
 int enqueue_post(simsense_handle *h, const float *masked, const uint8_t *flags_pre, const simsense_outputs *o,
                  hipStream_t s);
 int profile_begin_call(simsense_handle *h);
@@ -164,6 +185,9 @@ struct simsense_handle {  // opaque to callers
     uint16_t *cost_best_m, *cost_second_m;
     float *disp_sub_m, *masked_m;
     ss::AggregateArgs *d_args_m;
+    // semi-global block matching: 16-bit path values fed from a block-cost volume
+    bool sgbm;
+    uint16_t *volume;
     void *block;
     void *census_l, *census_r;
     uint8_t *paths[8];

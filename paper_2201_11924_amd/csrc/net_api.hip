@@ -370,6 +370,7 @@ int simsense_learned_compute(simsense_handle *h, simsense_net *n, const uint8_t 
     const simsense_params &p = h->p;
     if (pitch < p.width) return SIMSENSE_ERR_INVALID_ARGUMENT;
     if ((int64_t)p.width * p.height > n->max_pixels) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    if (p.block_w * p.block_h > 1) return SIMSENSE_ERR_UNSUPPORTED;  // the net was trained on SGM costs
     hipStream_t s = (hipStream_t)stream;
     n->last_stream = s;
     const int64_t P = (int64_t)p.width * p.height;

@@ -37,12 +37,53 @@ __device__ __forceinline__ uint32_t row_min(uint32_t v)
 constexpr int kSelBlock = 512;                            // one image row per block
 constexpr int kSelGroups = kSelBlock / kLanesPerLine;     // pixels in flight per row
 
-// the dpl path-value bytes of one direction for this lane, as packed words
-template <int DPL>
+// the dpl path values of one direction for this lane, as packed words: bytes,
+// or 16-bit values (V16, block matching)
+template <int DPL, bool V16 = false>
 struct Words {
-    static constexpr int N = (DPL + 3) / 4;
+    static constexpr int N = V16 ? (DPL + 1) / 2 : (DPL + 3) / 4;
     uint32_t w[N];
 };
+
+template <int DPL>
+__device__ __forceinline__ void load_words(const uint8_t *src, Words<DPL, true> &o)
+{
+    if constexpr (DPL == 1) {
+        o.w[0] = *(const uint16_t *)src;
+    } else if constexpr (DPL % 8 == 0) {
+#pragma unroll
+        for (int i = 0; i < DPL / 2; i += 4) {
+            const uint4 v = *(const uint4 *)(src + 4 * i);
+            o.w[i] = v.x; o.w[i + 1] = v.y; o.w[i + 2] = v.z; o.w[i + 3] = v.w;
+        }
+    } else if constexpr (DPL % 4 == 0) {
+#pragma unroll
+        for (int i = 0; i < DPL / 2; i += 2) {
+            const uint2 v = *(const uint2 *)(src + 4 * i);
+            o.w[i] = v.x; o.w[i + 1] = v.y;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < DPL / 2; ++i) o.w[i] = *(const uint32_t *)(src + 4 * i);
+    }
+}
+
+// 16-bit path values: a sum of 8 directions stays below 2^16 (the parameters
+// bound each value by 8191), so packed pairs add as whole words
+template <int DPL, int NDIR>
+__device__ __forceinline__ void sum_paths16(const Words<DPL, true> (&v)[NDIR], uint32_t (&S)[DPL])
+{
+    constexpr int N = Words<DPL, true>::N;
+    uint32_t acc[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        acc[k] = 0;
+#pragma unroll
+        for (int r = 0; r < NDIR; ++r) acc[k] += v[r].w[k];
+    }
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) S[j] = (j & 1) ? (acc[j / 2] >> 16) : (acc[j / 2] & 0xFFFFu);
+}
 
 template <int DPL>
 __device__ __forceinline__ void load_words(const uint8_t *src, Words<DPL> &o)
@@ -192,9 +233,10 @@ constexpr size_t select_lds_bytes(int W)
     return (size_t)kSelGroups * kLanesPerLine * DPL * 2 + ((size_t)kLanesPerLine * DPL + W) * 4 + (size_t)W * 10;
 }
 
-template <int DPL, int NDIR, bool SMALL>
+template <int DPL, int NDIR, bool SMALL, bool V16 = false>
 __device__ __forceinline__ void select_row(const SelectArgs &a, int y, uint32_t *smem)
 {
+    constexpr int kValBytes = V16 ? 2 : 1;
     constexpr int kDpad = kLanesPerLine * DPL;
     const int W = a.W, D = a.D;
     // LDS: per pixel group a row of S (16-bit); right-image keys indexed by
@@ -215,20 +257,21 @@ __device__ __forceinline__ void select_row(const SelectArgs &a, int y, uint32_t 
     const int lane = threadIdx.x % kLanesPerLine, group = threadIdx.x / kLanesPerLine;
     const int d0 = lane * DPL;
     uint16_t *my = srow + group * kDpad;
-    Words<DPL> cur[NDIR], nxt[NDIR];
+    Words<DPL, V16> cur[NDIR], nxt[NDIR];
     if (group < W) {
 #pragma unroll
-        for (int r = 0; r < NDIR; ++r) load_words<DPL>(a.paths[r] + (row + group) * kDpad + d0, cur[r]);
+        for (int r = 0; r < NDIR; ++r) load_words<DPL>(a.paths[r] + ((row + group) * kDpad + d0) * kValBytes, cur[r]);
     }
     for (int x = group; x < W; x += kSelGroups) {
         // look-ahead loads are unconditional (clamped to the row's last pixel)
         const int xn = min(x + kSelGroups, W - 1);
 #pragma unroll
-        for (int r = 0; r < NDIR; ++r) load_words<DPL>(a.paths[r] + (row + xn) * kDpad + d0, nxt[r]);
+        for (int r = 0; r < NDIR; ++r) load_words<DPL>(a.paths[r] + ((row + xn) * kDpad + d0) * kValBytes, nxt[r]);
         uint32_t S[DPL];
-        sum_paths<DPL, NDIR, SMALL>(cur, S);
+        if constexpr (V16) sum_paths16<DPL, NDIR>(cur, S);
+        else sum_paths<DPL, NDIR, SMALL>(cur, S);
         if (D < kDpad) {
-            // padding disparities: a cost above every real one (real S < 2^11)
+            // padding disparities: a cost above every real one (real S < 2^16 - 8)
 #pragma unroll
             for (int j = 0; j < DPL; ++j) S[j] = d0 + j < D ? S[j] : 0xFFFFu;
         }
@@ -295,11 +338,11 @@ __device__ __forceinline__ void select_row(const SelectArgs &a, int y, uint32_t 
     }
 }
 
-template <int DPL, int NDIR, bool SMALL>
+template <int DPL, int NDIR, bool SMALL, bool V16>
 __global__ __launch_bounds__(kSelBlock) void select_kernel(SelectArgs a)
 {
     extern __shared__ uint32_t smem[];
-    select_row<DPL, NDIR, SMALL>(a, (int)blockIdx.x, smem);
+    select_row<DPL, NDIR, SMALL, V16>(a, (int)blockIdx.x, smem);
 }
 
 // batch form: one block per (pair slot, row) item
@@ -318,8 +361,9 @@ void launch_sel3(const SelectArgs *a, const SelectBatch *b, bool small, hipStrea
     dim3 block(kSelBlock);
     if (a) {
         const size_t lds = select_lds_bytes<DPL>(a->W);
-        if (small) hipLaunchKernelGGL((select_kernel<DPL, NDIR, true>), dim3(a->H), block, lds, s, *a);
-        else hipLaunchKernelGGL((select_kernel<DPL, NDIR, false>), dim3(a->H), block, lds, s, *a);
+        if (a->values16) hipLaunchKernelGGL((select_kernel<DPL, NDIR, false, true>), dim3(a->H), block, lds, s, *a);
+        else if (small) hipLaunchKernelGGL((select_kernel<DPL, NDIR, true, false>), dim3(a->H), block, lds, s, *a);
+        else hipLaunchKernelGGL((select_kernel<DPL, NDIR, false, false>), dim3(a->H), block, lds, s, *a);
     } else {
         const size_t lds = select_lds_bytes<DPL>(b->max_width);
         if (small) hipLaunchKernelGGL((select_batch_kernel<DPL, NDIR, true>), dim3(b->nitems), block, lds, s, *b);
@@ -426,25 +470,26 @@ hipError_t launch_post_batch(const PostBatch &b, hipStream_t s)
 }
 
 // ---------------------------------------------------------------- debug volume
-__global__ __launch_bounds__(256) void volume_sum_kernel(PathSet paths, int ndirs,
+__global__ __launch_bounds__(256) void volume_sum_kernel(PathSet paths, int ndirs, int values16,
                                                          size_t npix, int D, int Dpad, uint16_t *out)
 {
     const size_t total = npix * D;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (size_t)gridDim.x * 256) {
         const size_t p = i / D, d = i - p * D;
         uint32_t s = 0;
-        for (int r = 0; r < ndirs; ++r) s += paths.p[r][p * Dpad + d];
+        for (int r = 0; r < ndirs; ++r)
+            s += values16 ? ((const uint16_t *)paths.p[r])[p * Dpad + d] : paths.p[r][p * Dpad + d];
         out[i] = (uint16_t)s;
     }
 }
 
-hipError_t launch_volume_sum(const PathSet &paths, int ndirs, int W, int H, int D, int Dpad,
+hipError_t launch_volume_sum(const PathSet &paths, int ndirs, bool values16, int W, int H, int D, int Dpad,
                              uint16_t *out, hipStream_t s)
 {
     size_t total = (size_t)W * H * D;
     size_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(volume_sum_kernel, dim3((unsigned)blocks), dim3(256), 0, s, paths, ndirs,
+    hipLaunchKernelGGL(volume_sum_kernel, dim3((unsigned)blocks), dim3(256), 0, s, paths, ndirs, (int)values16,
                        (size_t)W * H, D, Dpad, out);
     return hipGetLastError();
 }

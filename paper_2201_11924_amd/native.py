@@ -32,7 +32,8 @@ PARAM_FIELDS = ("width", "height", "max_disp", "census_w", "census_h", "census_m
 
 class Params(ct.Structure):
     _fields_ = [("struct_size", ct.c_uint32)] + [(n, ct.c_int32) for n in PARAM_FIELDS] + [
-        ("focal_px", ct.c_float), ("baseline_m", ct.c_float), ("lr_mode", ct.c_int32)]
+        ("focal_px", ct.c_float), ("baseline_m", ct.c_float), ("lr_mode", ct.c_int32),
+        ("block_w", ct.c_int32), ("block_h", ct.c_int32)]
 
     @classmethod
     def from_dict(cls, d: Dict) -> "Params":
@@ -43,6 +44,8 @@ class Params(ct.Structure):
         p.focal_px = float(d["focal_px"])
         p.baseline_m = float(d["baseline_m"])
         p.lr_mode = int(d.get("lr_mode", 0))
+        p.block_w = int(d.get("block_w", 1))
+        p.block_h = int(d.get("block_h", 1))
         return p
 
 

@@ -191,7 +191,7 @@ def test_full_right_reference_lr_matches_oracle(orc, nat, W, H, D, paths, kw):
     spec = PairSpec(W, H, planes=3, dmin=0, dmax=max(0.0, min(D - 1, W - 1) * 0.8), noise="gauss", sigma=3.0)
     left, right = noisy_pair(orc, spec, 3 * W + 5 * H + D)
     params = params_for(W, H, D, num_paths=paths, lr_mode=1, **kw)
-    ref, g = compare(orc, nat, params, left, right, label=f"lr_mode=1 {kw}")
+    ref, g = compare(orc, nat, params, left, right, volume=True, label=f"lr_mode=1 {kw}")
     import torch
     ss = nat.SimSense(params)
     ss.set_tuning(0, 0)
@@ -200,3 +200,31 @@ def test_full_right_reference_lr_matches_oracle(orc, nat, W, H, D, paths, kw):
     assert np.array_equal(host(out["disp_right"]), ref.dright.astype(np.uint8))
     assert np.array_equal(host(out["flags"]), ref.flags)
     ss.close()
+
+
+@pytest.mark.parametrize("W,H,D,kw", [
+    (96, 40, 32, dict(census_w=5, census_h=5, p1=20, p2=120, block_w=3, block_h=3)),
+    (173, 61, 64, dict(block_w=3, block_h=3, p1=30, p2=300)),
+    (61, 45, 37, dict(block_w=5, block_h=3, p1=40, p2=400, num_paths=4)),
+    (64, 33, 100, dict(census_w=3, census_h=3, census_mode=1, block_w=7, block_h=5, p1=50, p2=600, num_paths=2)),
+    (50, 29, 24, dict(block_w=3, block_h=5, p1=30, p2=300, lr_mode=1)),
+    (1, 20, 3, dict(block_w=3, block_h=3, p1=30, p2=300)), (40, 1, 8, dict(block_w=5, block_h=1, p1=30, p2=300)),
+    (64, 48, 256, dict(census_w=5, census_h=5, block_w=3, block_h=3, p1=20, p2=120)),
+])
+def test_sgbm_matches_oracle(orc, nat, W, H, D, kw):
+    """Semi-global block matching (block-summed Hamming cost, 16-bit path values)
+    against the oracle: every integer result bit-exact, the summed volume
+    included, sub-pixel and final disparities within 1e-5 px."""
+    spec = PairSpec(W, H, planes=3, dmin=0, dmax=max(0.0, min(D - 1, W - 1) * 0.8), noise="gauss", sigma=3.0)
+    left, right = noisy_pair(orc, spec, 7 * W + 3 * H + D)
+    compare(orc, nat, params_for(W, H, D, **kw), left, right, volume=True, label=f"sgbm {kw}")
+
+
+def test_sgbm_parameter_bounds(nat):
+    p = params_for(64, 32, 32, block_w=3, block_h=3, p1=30, p2=300)
+    nat.SimSense(p).close()
+    for bad in (dict(block_w=2), dict(block_h=33), dict(p2=8000), dict(block_w=1, block_h=1, p2=300)):
+        with pytest.raises(nat.SimSenseError):
+            nat.SimSense(dict(p, **bad))
+    with pytest.raises(nat.SimSenseError):
+        nat.Batch([p])
