@@ -17,16 +17,17 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sgm_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "noise_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (no fast-math, no FMA contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in _SRCS):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-                               "-fno-fast-math", "-Wall", "-o", tmp, _SRC, "-lm"])
+                               "-fno-fast-math", "-Wall", "-o", tmp, *_SRCS, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -190,6 +191,36 @@ def depth(disp: np.ndarray, focal_px: float, baseline_m: float) -> np.ndarray:
     lib().orc_depth(_p(disp), ct.c_int64(disp.size), ct.c_double(focal_px), ct.c_double(baseline_m),
                     _p(out))
     return out
+
+
+# ----------------------------------------------------------------- noise generator
+class OrcNoiseParams(ct.Structure):
+    _fields_ = [("gain_model", ct.c_int32), ("k", ct.c_float), ("theta", ct.c_float), ("gain_sd", ct.c_float),
+                ("mu", ct.c_float), ("sigma", ct.c_float), ("scale", ct.c_float),
+                ("seed_lo", ct.c_uint32), ("seed_hi", ct.c_uint32), ("stream", ct.c_uint32)]
+
+
+def philox4x32_10(counter, key):
+    c = (ct.c_uint32 * 4)(*counter)
+    k = (ct.c_uint32 * 2)(*key)
+    o = (ct.c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, k, o)
+    return [int(v) for v in o]
+
+
+def u01(x: int) -> float:
+    lib().orc_u01.restype = ct.c_double
+    return float(lib().orc_u01(ct.c_uint32(x)))
+
+
+def noise_draws(count: int, gain_model: int, k: float = 3.98, theta: float = 0.254, gain_sd: float = 0.05,
+                mu: float = -0.231, sigma: float = 0.83, scale: float = 1.0, seed: int = 0, stream: int = 0):
+    """gamma' and n' (float32) of pixels 0..count-1, as the on-device generator defines them."""
+    p = OrcNoiseParams(gain_model, k, theta, gain_sd, mu, sigma, scale, seed & 0xFFFFFFFF, seed >> 32, stream)
+    g = np.empty(count, np.float32)
+    n = np.empty(count, np.float32)
+    lib().orc_noise_draws(ct.byref(p), ct.c_int64(count), _p(g), _p(n))
+    return g, n
 
 
 @dataclass
