@@ -244,6 +244,8 @@ def learned_and_batch_legs(nat, args, out, inputs):
 # Sec. VI-D, Table II: SGM frames/s of the paper's implementation at 960x540 with
 # 4 paths on an NVIDIA RTX 4090 (another GPU; quoted as context only)
 PAPER_TABLE2_SGM_FPS = {64: 414.51, 96: 326.79, 128: 281.26, 256: 147.13}
+PAPER_TABLE2_SGBM_FPS = {64: 342.24, 96: 268.98, 128: 232.49, 256: 128.56}
+SGBM_BLOCK = 3  # the paper gives no block size; penalties scale with the block area
 
 
 def paper_shape_leg(nat, reps=100):
@@ -252,32 +254,35 @@ def paper_shape_leg(nat, reps=100):
     from synth import make_pair, pair_seed
     from synth.stereo import c1_like
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
-    res = {}
+    res, res_b = {}, {}
     for i, D in enumerate(sorted(PAPER_TABLE2_SGM_FPS)):
         cfg = c1_like(960, 540, D)
-        params = dict(cfg["params"], num_paths=4)
         pr = make_pair(cfg["spec"], pair_seed(5, i))
         L = nat.ir_noise(t(pr.left), t(pr.gamma_l), t(pr.n_l))
         R = nat.ir_noise(t(pr.right), t(pr.gamma_r), t(pr.n_r))
-        ss = nat.SimSense(params)
         depth = torch.empty((540, 960), dtype=torch.float32, device="cuda")
-        for _ in range(10):
-            ss.compute(L, R, depth)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            ss.compute(L, R, depth)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        ss.close()
-        fps = 1000.0 / ms
-        res[f"D{D}"] = {"fps": round(fps, 1), "ms": round(ms, 4),
-                        "mpix_disp_per_s": round(960 * 540 * D * fps / 1e6, 1),
-                        "paper_fps_rtx4090": PAPER_TABLE2_SGM_FPS[D]}
+        a = SGBM_BLOCK * SGBM_BLOCK
+        sgm = dict(cfg["params"], num_paths=4)
+        sgbm = dict(sgm, block_w=SGBM_BLOCK, block_h=SGBM_BLOCK, p1=sgm["p1"] * a, p2=sgm["p2"] * a)
+        for params, out, paper in ((sgm, res, PAPER_TABLE2_SGM_FPS), (sgbm, res_b, PAPER_TABLE2_SGBM_FPS)):
+            ss = nat.SimSense(params)
+            for _ in range(10):
+                ss.compute(L, R, depth)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                ss.compute(L, R, depth)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            ss.close()
+            fps = 1000.0 / ms
+            out[f"D{D}"] = {"fps": round(fps, 1), "ms": round(ms, 4),
+                            "mpix_disp_per_s": round(960 * 540 * D * fps / 1e6, 1), "paper_fps_rtx4090": paper[D]}
     return {"shape": "960x540, 4 paths, census 7x9 CS, depth output at 960x540 (the paper's 1920x1080 "
-                     "registration is not part of this path)", "by_max_disp": res}
+                     "registration is not part of this path)", "by_max_disp": res,
+            "sgbm": {"block": f"{SGBM_BLOCK}x{SGBM_BLOCK}, P1/P2 x {SGBM_BLOCK * SGBM_BLOCK}", "by_max_disp": res_b}}
 
 
 def main():

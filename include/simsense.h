@@ -138,6 +138,66 @@ int simsense_compute_ex(simsense_handle *h, const uint8_t *left, const uint8_t *
 int simsense_ir_noise(const uint8_t *in, const float *gamma, const float *n, uint8_t *out,
                       int64_t count, void *stream);
 
+/* On-device IR noise for simulated cameras (Sec. VI-C: I' = gamma * I + n, Eq. (7);
+ * Eq. (8) and the D415 fit of Sec. VII-C give the distributions, Table X the noise
+ * scale).  Draws come from Philox4x32-10 (Salmon et al., SC'11) with counter
+ * (pixel index y*width+x, stream, attempt, 0) and key (seed low, seed high), so
+ * they depend only on (seed, stream, pixel).
+ *  gain_model  0: gamma = 1; 1: gamma ~ Gamma(k, theta), k >= 1, by the method of
+ *              Marsaglia and Tsang (at most 64 attempts, then the mode-free value
+ *              (k - 1/3) theta); 2: gamma ~ Normal(1, gain_sd^2).
+ *  mu, sigma   n ~ Normal(mu, sigma^2) in DN (Box-Muller).
+ *  scale       s >= 0: gamma' = 1 + s (gamma - 1), n' = s n (1 = the fitted noise).
+ * Uniforms are ((x >> 9) + 0.5) 2^-23; normals and gammas are computed in double
+ * and rounded to float32; gamma' and n' are formed in float32. */
+typedef struct simsense_noise_params {
+    uint32_t struct_size;
+    int32_t gain_model;
+    float k, theta, gain_sd;
+    float mu, sigma;
+    float scale;
+    uint64_t seed;
+    uint32_t stream;
+} simsense_noise_params;
+
+/* gamma' and n' of pixels 0..count-1 (device float arrays; count <= 2^32). */
+int simsense_noise_draws(const simsense_noise_params *params, int64_t count, float *gamma, float *n, void *stream);
+
+/* Draws and applies the noise in one pass: out = clip(rint(gamma' * in + n')), the
+ * product and the sum each rounded to float32, ties to even, clipped to [0, 255]
+ * (the arithmetic of simsense_ir_noise).  Images are device uint8, row pitches in
+ * bytes (>= width); width, height <= 65536.  Asynchronous on `stream`. */
+int simsense_ir_noise_generate(const simsense_noise_params *params, const uint8_t *in, int32_t in_pitch,
+                               int32_t width, int32_t height, uint8_t *out, int32_t out_pitch, void *stream);
+
+/* The steps either side of the matching that Sec. VI-D integrates with it.
+ *
+ * Rectification: out(x, y) = bilinear sample of `in` at (map_x(x,y), map_y(x,y)),
+ * the per-pixel source coordinates a calibration tool produces (device float32,
+ * out_w x out_h, pitch out_w); sources outside [0, in_w-1] x [0, in_h-1] give 0.
+ * Evaluated in float32 as top = i00 + fx (i01 - i00), bottom likewise, then
+ * top + fy (bottom - top), every operation rounded, then rounded to the nearest
+ * integer (ties to even) and clipped to [0, 255].  Images are device uint8 with
+ * row pitches in bytes. */
+int simsense_rectify(const uint8_t *in, int32_t in_pitch, int32_t in_w, int32_t in_h, const float *map_x,
+                     const float *map_y, int32_t out_w, int32_t out_h, uint8_t *out, int32_t out_pitch, void *stream);
+
+/* Pinhole intrinsics in pixels. */
+typedef struct simsense_camera {
+    float fx, fy, cx, cy;
+} simsense_camera;
+
+/* Depth registration into the RGB camera.  Every pixel (u, v) of `depth` (device
+ * float32, width x height, pitch width; the rectified left IR camera) with z > 0 is
+ * back-projected, X = (u-cx) z / fx, Y = (v-cy) z / fy, Z = z, moved by `rt` (host,
+ * 12 floats: R row-major then t; X' = R X + t with each row summed left to right),
+ * dropped if Z' <= 0, projected with `rgb`, rounded to the nearest pixel (ties to
+ * even) and z-buffered: out (device float32, out_w x out_h) holds the smallest Z'
+ * per pixel, 0 where no point lands.  All float32, operation by operation. */
+int simsense_register_depth(const float *depth, int32_t width, int32_t height, const simsense_camera *ir,
+                            const float *rt, const simsense_camera *rgb, int32_t out_w, int32_t out_h, float *out,
+                            void *stream);
+
 /* Census transform alone (Sec. VI-D): one uint64 word per pixel, bit k = k-th
  * comparison of the window enumerated row-major from its top-left corner;
  * samples outside the image clamp to the edge.  Uses width, height and the

@@ -214,9 +214,9 @@ def u01(x: int) -> float:
 
 
 def noise_draws(count: int, gain_model: int, k: float = 3.98, theta: float = 0.254, gain_sd: float = 0.05,
-                mu: float = -0.231, sigma: float = 0.83, scale: float = 1.0, seed: int = 0, stream: int = 0):
+                mu: float = -0.231, sigma: float = 0.83, scale: float = 1.0, seed: int = 0, noise_stream: int = 0):
     """gamma' and n' (float32) of pixels 0..count-1, as the on-device generator defines them."""
-    p = OrcNoiseParams(gain_model, k, theta, gain_sd, mu, sigma, scale, seed & 0xFFFFFFFF, seed >> 32, stream)
+    p = OrcNoiseParams(gain_model, k, theta, gain_sd, mu, sigma, scale, seed & 0xFFFFFFFF, seed >> 32, noise_stream)
     g = np.empty(count, np.float32)
     n = np.empty(count, np.float32)
     lib().orc_noise_draws(ct.byref(p), ct.c_int64(count), _p(g), _p(n))

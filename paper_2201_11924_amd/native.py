@@ -227,6 +227,41 @@ def ir_noise(img: torch.Tensor, gamma: torch.Tensor, n: torch.Tensor, out: Optio
     return out
 
 
+class NoiseParams(ct.Structure):
+    _fields_ = [("struct_size", ct.c_uint32), ("gain_model", ct.c_int32), ("k", ct.c_float), ("theta", ct.c_float),
+                ("gain_sd", ct.c_float), ("mu", ct.c_float), ("sigma", ct.c_float), ("scale", ct.c_float),
+                ("seed", ct.c_uint64), ("stream", ct.c_uint32)]
+
+    @classmethod
+    def make(cls, gain_model: int, k: float = 3.98, theta: float = 0.254, gain_sd: float = 0.05, mu: float = -0.231,
+             sigma: float = 0.83, scale: float = 1.0, seed: int = 0, noise_stream: int = 0) -> "NoiseParams":
+        return cls(ct.sizeof(cls), gain_model, k, theta, gain_sd, mu, sigma, scale, seed, noise_stream)
+
+
+_lib.simsense_noise_draws.argtypes = [ct.POINTER(NoiseParams), _i64, _vp, _vp, _vp]
+_lib.simsense_ir_noise_generate.argtypes = [ct.POINTER(NoiseParams), _vp, _i32, _i32, _i32, _vp, _i32, _vp]
+
+
+def noise_draws(count: int, stream=None, **kw):
+    """gamma' and n' of pixels 0..count-1 from the on-device generator (GPU tensors)."""
+    p = NoiseParams.make(**kw)
+    g = torch.empty(count, dtype=torch.float32, device="cuda")
+    n = torch.empty(count, dtype=torch.float32, device="cuda")
+    _check(_lib.simsense_noise_draws(ct.byref(p), count, _ptr(g), _ptr(n), _stream(stream)), "simsense_noise_draws")
+    return g, n
+
+
+def ir_noise_generate(img: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None, **kw) -> torch.Tensor:
+    """IR noise of Sec. VI-C drawn on the device and applied in one pass."""
+    _need(img, torch.uint8, img.shape, "img")
+    H, W = img.shape
+    out = torch.empty_like(img) if out is None else out
+    p = NoiseParams.make(**kw)
+    _check(_lib.simsense_ir_noise_generate(ct.byref(p), _ptr(img), W, W, H, _ptr(out), W, _stream(stream)),
+           "simsense_ir_noise_generate")
+    return out
+
+
 def census(params: Dict, img: torch.Tensor, stream=None) -> torch.Tensor:
     p = Params.from_dict(params)
     H, W = params["height"], params["width"]

@@ -25,22 +25,22 @@ def test_uniform_conversion(orc):
     (2, stats.norm(loc=1.0, scale=0.05)),
 ])
 def test_gain_distributions(orc, model, dist):
-    g, n = orc.noise_draws(100_000, model, seed=12345, stream=3)
+    g, n = orc.noise_draws(100_000, model, seed=12345, noise_stream=3)
     assert stats.kstest(g.astype(np.float64), dist.cdf).pvalue > 1e-3
     assert abs(g.mean() - dist.mean()) < 5 * dist.std() / np.sqrt(g.size)
     assert stats.kstest(n.astype(np.float64), stats.norm(loc=-0.231, scale=0.83).cdf).pvalue > 1e-3
-    g0, n0 = orc.noise_draws(1000, 0, seed=12345, stream=3)
+    g0, n0 = orc.noise_draws(1000, 0, seed=12345, noise_stream=3)
     assert (g0 == 1.0).all() and np.array_equal(n0, n[:1000])
 
 
 def test_counter_based_and_scale(orc):
-    g, n = orc.noise_draws(5000, 1, seed=7, stream=1)
-    g2, n2 = orc.noise_draws(300, 1, seed=7, stream=1)
+    g, n = orc.noise_draws(5000, 1, seed=7, noise_stream=1)
+    g2, n2 = orc.noise_draws(300, 1, seed=7, noise_stream=1)
     assert np.array_equal(g[:300], g2) and np.array_equal(n[:300], n2)  # depends on the pixel only
-    g3, _ = orc.noise_draws(300, 1, seed=7, stream=2)
+    g3, _ = orc.noise_draws(300, 1, seed=7, noise_stream=2)
     assert not np.array_equal(g2, g3)
-    gz, nz = orc.noise_draws(5000, 1, seed=7, stream=1, scale=0.0)
+    gz, nz = orc.noise_draws(5000, 1, seed=7, noise_stream=1, scale=0.0)
     assert (gz == 1.0).all() and (nz == 0.0).all()
-    gh, nh = orc.noise_draws(5000, 1, seed=7, stream=1, scale=0.5)
+    gh, nh = orc.noise_draws(5000, 1, seed=7, noise_stream=1, scale=0.5)
     assert np.allclose(gh - 1.0, 0.5 * (g.astype(np.float64) - 1.0), atol=1e-6)
     assert np.allclose(nh, 0.5 * n.astype(np.float64), atol=1e-6)
