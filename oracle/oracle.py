@@ -17,7 +17,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sgm_oracle.c")
-_SRCS = [_SRC, os.path.join(_HERE, "noise_oracle.c")]
+_SRCS = [_SRC, os.path.join(_HERE, "noise_oracle.c"), os.path.join(_HERE, "geometry_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -221,6 +221,33 @@ def noise_draws(count: int, gain_model: int, k: float = 3.98, theta: float = 0.2
     n = np.empty(count, np.float32)
     lib().orc_noise_draws(ct.byref(p), ct.c_int64(count), _p(g), _p(n))
     return g, n
+
+
+# ----------------------------------------------------------------- rectification, registration
+def rectify(img: np.ndarray, map_x: np.ndarray, map_y: np.ndarray) -> np.ndarray:
+    img = np.ascontiguousarray(img, np.uint8)
+    map_x = np.ascontiguousarray(map_x, np.float32)
+    map_y = np.ascontiguousarray(map_y, np.float32)
+    H, W = img.shape
+    oh, ow = map_x.shape
+    out = np.empty((oh, ow), np.uint8)
+    lib().orc_rectify(_p(img), W, W, H, _p(map_x), _p(map_y), ow, oh, _p(out))
+    return out
+
+
+class OrcCamera(ct.Structure):
+    _fields_ = [("fx", ct.c_float), ("fy", ct.c_float), ("cx", ct.c_float), ("cy", ct.c_float)]
+
+
+def register_depth(depth: np.ndarray, ir, rt, rgb, out_w: int, out_h: int) -> np.ndarray:
+    """ir, rgb: (fx, fy, cx, cy); rt: 12 floats, R row-major then t."""
+    depth = np.ascontiguousarray(depth, np.float32)
+    H, W = depth.shape
+    rt = np.ascontiguousarray(rt, np.float32).reshape(12)
+    out = np.empty((out_h, out_w), np.float32)
+    lib().orc_register_depth(_p(depth), W, H, ct.byref(OrcCamera(*ir)), _p(rt), ct.byref(OrcCamera(*rgb)),
+                             out_w, out_h, _p(out))
+    return out
 
 
 @dataclass
