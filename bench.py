@@ -280,6 +280,33 @@ def paper_shape_leg(nat, reps=100):
             fps = 1000.0 / ms
             out[f"D{D}"] = {"fps": round(fps, 1), "ms": round(ms, 4),
                             "mpix_disp_per_s": round(960 * 540 * D * fps / 1e6, 1), "paper_fps_rtx4090": paper[D]}
+            if params is sgm:
+                # the paper's whole timed chain: rectify both raw images, match, register
+                # the depth into a 1920x1080 RGB camera
+                ys, xs = torch.meshgrid(torch.arange(540, device="cuda", dtype=torch.float32),
+                                        torch.arange(960, device="cuda", dtype=torch.float32), indexing="ij")
+                mx, my = (xs + 0.37).contiguous(), (ys - 0.21).contiguous()
+                ir = (params["focal_px"] * 0.75, params["focal_px"] * 0.75, 479.5, 269.5)
+                rgb = (1380.0, 1380.0, 959.5, 539.5)
+                rt = [1, 0, 0, 0, 1, 0, 0, 0, 1, -0.015, 0.0, 0.0]
+                ss = nat.SimSense(params)
+
+                def chain():
+                    Lr = nat.rectify(L, mx, my)
+                    Rr = nat.rectify(R, mx, my)
+                    ss.compute(Lr, Rr, depth)
+                    return nat.register_depth(depth, ir, rt, rgb, 1920, 1080)
+                for _ in range(10):
+                    chain()
+                torch.cuda.synchronize()
+                e0.record()
+                for _ in range(reps):
+                    chain()
+                e1.record()
+                torch.cuda.synchronize()
+                msc = e0.elapsed_time(e1) / reps
+                ss.close()
+                out[f"D{D}"]["fps_rectify_match_register_1920x1080"] = round(1000.0 / msc, 1)
     return {"shape": "960x540, 4 paths, census 7x9 CS, depth output at 960x540 (the paper's 1920x1080 "
                      "registration is not part of this path)", "by_max_disp": res,
             "sgbm": {"block": f"{SGBM_BLOCK}x{SGBM_BLOCK}, P1/P2 x {SGBM_BLOCK * SGBM_BLOCK}", "by_max_disp": res_b}}

@@ -336,6 +336,40 @@ __device__ __forceinline__ void window_at(const BlockGeom &g, int t, int &row, i
 // line's first pixel, exactly the state a line starts from.  Lanes of lines that
 // have ended (or not started) store into one spare pixel after the image, so
 // every step issues the same unconditional store.
+// Census words are read from the LDS tile with inline-assembly ds_read_b32: the
+// tile is filled by direct-to-LDS loads, and for compiler-visible LDS reads the
+// compiler would wait for every outstanding vector memory operation (those loads
+// and all path-value stores) before each read.  The tile's readiness is already
+// guaranteed by the explicit vmcnt wait and barrier at each chunk boundary, so the
+// reads need only their own LDS counter: lds_wait() waits for it and ties the
+// results to that wait.
+template <int OFF>
+__device__ __forceinline__ uint32_t ds_read_at(uint32_t addr)
+{
+    uint32_t v;
+    asm volatile("ds_read_b32 %0, %1 offset:%2" : "=v"(v) : "v"(addr), "i"(OFF));
+    return v;
+}
+
+template <int N, int J = 0>
+__device__ __forceinline__ void ds_read_run(uint32_t addr, uint32_t (&w)[N])
+{
+    if constexpr (J < N) {
+        w[J] = ds_read_at<4 * J>(addr);
+        ds_read_run<N, J + 1>(addr, w);
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void lds_wait(uint32_t &a, uint32_t (&w)[N])
+{
+    asm volatile("s_waitcnt lgkmcnt(0)" : "+v"(a));
+#pragma unroll
+    for (int j = 0; j < N; ++j) asm volatile("" : "+v"(w[j]));
+}
+
+__device__ __forceinline__ uint32_t lds_addr(const void *p) { return (uint32_t)(size_t)p; }
+
 // The scalars one block of lines needs, each made explicitly wavefront-uniform
 // (readfirstlane) so that they live in scalar registers even when they were read
 // from a work list in memory, which the compiler cannot prove uniform.
@@ -442,10 +476,19 @@ __device__ __forceinline__ void run_lines(const LineArgs &a, const BlockGeom &g,
     // census words of one clock: cL(x) and cR(x - d) for d = d0 + DPL - 1 .. d0
     auto fetch = [&](int buf, int slot, int xo, Word &wl, Word(&wr)[DPL]) {
         const Word *sl = (const Word *)&tile[buf][0] + slot * kSlot;
-        wl = sl[kDpad + kChunk - 1 + xo];
-        const Word *p = sl + (xo + kDpad - d0 - DPL);
+        if constexpr (WIDE) {
+            wl = sl[kDpad + kChunk - 1 + xo];
+            const Word *p = sl + (xo + kDpad - d0 - DPL);
 #pragma unroll
-        for (int j = 0; j < DPL; ++j) wr[j] = p[j];
+            for (int j = 0; j < DPL; ++j) wr[j] = p[j];
+        } else {
+            wl = ds_read_at<0>(lds_addr(sl + kDpad + kChunk - 1 + xo));
+            ds_read_run<DPL>(lds_addr(sl + (xo + kDpad - d0 - DPL)), wr);
+        }
+    };
+    // the words of a fetch may be used only after this
+    auto ready = [&](Word &wl, Word(&wr)[DPL]) {
+        if constexpr (!WIDE) lds_wait<DPL>(wl, wr);
     };
 
     uint32_t Q[DPL];
@@ -477,6 +520,7 @@ __device__ __forceinline__ void run_lines(const LineArgs &a, const BlockGeom &g,
             const int s = t - skew;
             int x, row, xm, slot;
             locate(c0, k, x, row, xm, slot);
+            ready(wl_n, wr_n);
             const Word wl = wl_n;
             Word wr[DPL];
 #pragma unroll
@@ -549,11 +593,16 @@ __device__ __forceinline__ void aggregate_block(const AggregateArgs &a, int blk,
 {
     constexpr int kDpad = kLanesPerLine * DPL;
     static_assert(kDpad % HL == 0, "horizontal lanes must divide the padded disparity count");
-    int dir = 0;
+    // the direction of block blk: the number of later directions whose first block
+    // it has passed (all prefix sums loaded at once, not one load per branch)
     const int ndirs = uniform(a.ndirs);
+    int bb[8];
 #pragma unroll
-    for (int k = 1; k < 8; ++k)
-        if (k < ndirs && blk >= uniform(a.block_begin[k])) dir = k;
+    for (int k = 0; k < 8; ++k) bb[k] = a.block_begin[k];
+    int dir = 0;
+#pragma unroll
+    for (int k = 1; k < 8; ++k) dir += (k < ndirs && blk >= bb[k]) ? 1 : 0;
+    dir = uniform(dir);
     LineArgs la;
     la.cl = uniform((const uint32_t *)a.census_l);
     la.cr = uniform((const uint32_t *)a.census_r);

@@ -262,6 +262,39 @@ def ir_noise_generate(img: torch.Tensor, out: Optional[torch.Tensor] = None, str
     return out
 
 
+class Camera(ct.Structure):
+    _fields_ = [("fx", ct.c_float), ("fy", ct.c_float), ("cx", ct.c_float), ("cy", ct.c_float)]
+
+
+_lib.simsense_rectify.argtypes = [_vp, _i32, _i32, _i32, _vp, _vp, _i32, _i32, _vp, _i32, _vp]
+_lib.simsense_register_depth.argtypes = [_vp, _i32, _i32, ct.POINTER(Camera), ct.POINTER(ct.c_float),
+                                         ct.POINTER(Camera), _i32, _i32, _vp, _vp]
+
+
+def rectify(img: torch.Tensor, map_x: torch.Tensor, map_y: torch.Tensor, stream=None) -> torch.Tensor:
+    """Bilinear remap of a raw IR image to the rectified frame (maps: float32, output shape)."""
+    H, W = img.shape
+    _need(img, torch.uint8, (H, W), "img")
+    oh, ow = map_x.shape
+    _need(map_x, torch.float32, (oh, ow), "map_x")
+    _need(map_y, torch.float32, (oh, ow), "map_y")
+    out = torch.empty((oh, ow), dtype=torch.uint8, device=img.device)
+    _check(_lib.simsense_rectify(_ptr(img), W, W, H, _ptr(map_x), _ptr(map_y), ow, oh, _ptr(out), ow,
+                                 _stream(stream)), "simsense_rectify")
+    return out
+
+
+def register_depth(depth: torch.Tensor, ir, rt, rgb, out_w: int, out_h: int, stream=None) -> torch.Tensor:
+    """Depth registered into the RGB camera; ir, rgb: (fx, fy, cx, cy); rt: 12 floats (R row-major, t)."""
+    H, W = depth.shape
+    _need(depth, torch.float32, (H, W), "depth")
+    rtv = (ct.c_float * 12)(*[float(v) for v in rt])
+    out = torch.empty((out_h, out_w), dtype=torch.float32, device=depth.device)
+    _check(_lib.simsense_register_depth(_ptr(depth), W, H, ct.byref(Camera(*ir)), rtv, ct.byref(Camera(*rgb)),
+                                        out_w, out_h, _ptr(out), _stream(stream)), "simsense_register_depth")
+    return out
+
+
 def census(params: Dict, img: torch.Tensor, stream=None) -> torch.Tensor:
     p = Params.from_dict(params)
     H, W = params["height"], params["width"]
