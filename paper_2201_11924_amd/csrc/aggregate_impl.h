@@ -14,10 +14,14 @@
 //   * the d-1 / d+1 neighbours from the lane's own registers, and at the lane
 //     edges through a row_shr / row_shl DPP move;
 //   * the path minimum m through a row_ror butterfly (4 DPP steps);
-// and the normalised state Q = L - m is kept in registers along the line.
-// With Q the update is L = C + min(Q(d), min(Q(d-1), Q(d+1)) + P1, P2), which
-// equals the recurrence above exactly; a line starts from Q = 0, which yields
-// L = C at its first pixel.
+// The lanes keep the un-normalised sums
+//   U(p,d) = C(p,d) + min(U(p-r,d), U(p-r,d+-1) + P1, u + P2),  u = min_k U(p-r,k),
+// for which induction gives L_r(p,d) = U(p,d) - u exactly (the subtraction of m
+// in the recurrence only shifts every value of a step by the same amount), so a
+// step needs no normalisation pass: the stored byte is U - u, written straight
+// into its byte of the output word (SDWA destination select).  A line starts
+// from U = 0, u = 0, which yields L = C at its first pixel; U grows by at most
+// bits + P2 per pixel, so 32 bits hold it for any line of the image.
 //
 // A 256-thread block owns 16 lines of one direction and advances them by one
 // "clock" at a time.  Lines are grouped so that at every clock the block's 16
@@ -41,7 +45,9 @@ namespace ss {
 
 namespace {
 
-constexpr uint32_t kInf = 0x10000000u;      // outside the disparity range
+// the neighbour value of a disparity outside the line (the identity of min: the
+// neighbour term min(v(d-1), v(d+1)) then takes the one neighbour that exists)
+constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kPadCost = 0x01000000u;  // cost of the padding disparities >= D
 constexpr int kChunk = 16;                  // clocks per LDS tile (= lines per block)
 static_assert(kChunk == kLinesPerBlock, "one tile slot per line");
@@ -73,48 +79,48 @@ __device__ __forceinline__ uint32_t row_min(uint32_t v)
     return v;
 }
 
-constexpr int kWaveShl1 = 0x130, kWaveShr1 = 0x138, kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+constexpr int kWaveShl1 = 0x130, kWaveShr1 = 0x138;
 
 // Cross-lane pieces of a line that spans LPL lanes (16: one DPP row, 32: half a
 // wave, 64: the whole wave).  Lanes hold consecutive disparity blocks.
 template <int LPL>
 struct LineOps {
-    // value of the previous lane (lane 0 of the line gets kInf)
+    // value of the previous lane (lane 0 of the line gets kNone)
     static __device__ __forceinline__ uint32_t from_prev(uint32_t v, bool first)
     {
         if constexpr (LPL == 16) {
-            return dpp_mov<kRowShr1>(kInf, v);
+            return dpp_mov<kRowShr1>(kNone, v);
         } else {
-            const uint32_t r = dpp_mov<kWaveShr1>(kInf, v);
-            return LPL == 32 && first ? kInf : r;
+            const uint32_t r = dpp_mov<kWaveShr1>(kNone, v);
+            return LPL == 32 && first ? kNone : r;
         }
     }
-    // value of the next lane (the line's last lane gets kInf)
+    // value of the next lane (the line's last lane gets kNone)
     static __device__ __forceinline__ uint32_t from_next(uint32_t v, bool last)
     {
         if constexpr (LPL == 16) {
-            return dpp_mov<kRowShl1>(kInf, v);
+            return dpp_mov<kRowShl1>(kNone, v);
         } else {
-            const uint32_t r = dpp_mov<kWaveShl1>(kInf, v);
-            return LPL == 32 && last ? kInf : r;
+            const uint32_t r = dpp_mov<kWaveShl1>(kNone, v);
+            return LPL == 32 && last ? kNone : r;
         }
     }
-    // minimum over the line's lanes, in every lane of the line
+    // minimum over the line's lanes, in every lane of the line: the DPP-row
+    // minimum, then rows exchanged in pairs (permlane16 swap: row 0 with row 1,
+    // row 2 with row 3) and, for a whole-wave line, halves exchanged (permlane32
+    // swap); a swap of a value with itself hands every lane its partner's value
     static __device__ __forceinline__ uint32_t line_min(uint32_t v)
     {
         v = row_min(v);
-        if constexpr (LPL == 16) {
-            return v;
-        } else if constexpr (LPL == 32) {
-            // rows 1 and 3 take the minimum with lane 15 of the row before them
-            v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, kRowBcast15, 0xA, 0xF, false));
-            const uint32_t lo = __builtin_amdgcn_readlane(v, 31), hi = __builtin_amdgcn_readlane(v, 63);
-            return (threadIdx.x & 32) ? hi : lo;
-        } else {
-            v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, kRowBcast15, 0xA, 0xF, false));
-            v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, kRowBcast31, 0xC, 0xF, false));
-            return __builtin_amdgcn_readlane(v, 63);
+        if constexpr (LPL >= 32) {
+            const auto s = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+            v = min((uint32_t)s[0], (uint32_t)s[1]);
         }
+        if constexpr (LPL == 64) {
+            const auto s = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+            v = min((uint32_t)s[0], (uint32_t)s[1]);
+        }
+        return v;
     }
 };
 
@@ -144,38 +150,82 @@ __device__ __forceinline__ void gstore(uint8_t *p, T v)
 typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 
-template <int DPL>
-__device__ __forceinline__ void store_bytes(uint8_t *dst, const uint32_t (&L)[DPL])
+typedef uint32_t u32x3_t __attribute__((ext_vector_type(3)));
+
+// byte B of w = the low byte of a - b, written in place by the subtraction
+// itself (SDWA destination select; byte 0 clears the rest of the word, bytes
+// 1..3 keep it)
+__device__ __forceinline__ void put_byte(uint32_t &w, uint32_t a, uint32_t b, int B)
 {
-    if constexpr (DPL % 4 == 0) {
-        uint32_t w[DPL / 4];
+    if (B == 0)
+        asm("v_sub_u32_sdwa %0, %1, %2 dst_sel:BYTE_0 dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:DWORD"
+            : "=v"(w) : "v"(a), "v"(b));
+    else if (B == 1)
+        asm("v_sub_u32_sdwa %0, %1, %2 dst_sel:BYTE_1 dst_unused:UNUSED_PRESERVE src0_sel:DWORD src1_sel:DWORD"
+            : "+v"(w) : "v"(a), "v"(b));
+    else if (B == 2)
+        asm("v_sub_u32_sdwa %0, %1, %2 dst_sel:BYTE_2 dst_unused:UNUSED_PRESERVE src0_sel:DWORD src1_sel:DWORD"
+            : "+v"(w) : "v"(a), "v"(b));
+    else
+        asm("v_sub_u32_sdwa %0, %1, %2 dst_sel:BYTE_3 dst_unused:UNUSED_PRESERVE src0_sel:DWORD src1_sel:DWORD"
+            : "+v"(w) : "v"(a), "v"(b));
+}
+
+// disparities packed per output word: 4 when dpl allows whole words, else
+// pairs (16-bit stores) or single bytes
+template <int DPL>
+__host__ __device__ constexpr int bytes_per_word()
+{
+    return DPL % 4 == 0 ? 4 : (DPL % 2 == 0 ? 2 : 1);
+}
+
+// The lane's dpl path values L = U - u as bytes at byte offset `off` of the
+// buffer rs (d0 .. d0 + dpl - 1 of one pixel).  Buffer stores take a 32-bit
+// offset, and one at or past the buffer's size is dropped by the hardware, so
+// a lane off its line passes such an offset instead of branching.
+template <int DPL>
+__device__ __forceinline__ void store_path(__amdgpu_buffer_rsrc_t rs, uint32_t off, const uint32_t (&U)[DPL], uint32_t u)
+{
+    constexpr int G = bytes_per_word<DPL>(), NW = DPL / G;
+    uint32_t w[NW];
 #pragma unroll
-        for (int k = 0; k < DPL / 4; ++k) {
-            // low bytes of L0..L3 into one word: two byte-pair gathers, then one merge
-            const uint32_t lo = __builtin_amdgcn_perm(L[4 * k + 1], L[4 * k], 0x0c0c0400u);
-            const uint32_t hi = __builtin_amdgcn_perm(L[4 * k + 3], L[4 * k + 2], 0x0c0c0400u);
-            w[k] = __builtin_amdgcn_perm(hi, lo, 0x05040100u);
-        }
-        if constexpr (DPL == 4) {
-            gstore(dst, w[0]);
-        } else if constexpr (DPL == 8) {
-            gstore(dst, u32x2_t{w[0], w[1]});
-        } else if constexpr (DPL == 12) {
-            gstore(dst, u32x2_t{w[0], w[1]});
-            gstore(dst + 8, w[2]);
+    for (int k = 0; k < NW; ++k)
+#pragma unroll
+        for (int b = 0; b < G; ++b) put_byte(w[k], U[G * k + b], u, b);
+    if constexpr (G == 4) {
+        if constexpr (NW == 1) {
+            __builtin_amdgcn_raw_buffer_store_b32(w[0], rs, off, 0, 0);
+        } else if constexpr (NW == 2) {
+            __builtin_amdgcn_raw_buffer_store_b64(u32x2_t{w[0], w[1]}, rs, off, 0, 0);
+        } else if constexpr (NW == 3) {
+            // 12 bytes at a 4-byte-aligned offset: two stores of natural width
+            __builtin_amdgcn_raw_buffer_store_b64(u32x2_t{w[0], w[1]}, rs, off, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(w[2], rs, off + 8, 0, 0);
         } else {
-            static_assert(DPL == 16, "unsupported disparities per lane");
-            gstore(dst, u32x4_t{w[0], w[1], w[2], w[3]});
+            static_assert(NW == 4, "unsupported disparities per lane");
+            __builtin_amdgcn_raw_buffer_store_b128(u32x4_t{w[0], w[1], w[2], w[3]}, rs, off, 0, 0);
         }
-    } else if constexpr (DPL % 2 == 0) {
+    } else if constexpr (G == 2) {
 #pragma unroll
-        for (int k = 0; k < DPL / 2; ++k)
-            gstore(dst + 2 * k, (uint16_t)((L[2 * k] & 0xFF) | ((L[2 * k + 1] & 0xFF) << 8)));
+        for (int k = 0; k < NW; ++k) __builtin_amdgcn_raw_buffer_store_b16((uint16_t)w[k], rs, off + 2 * k, 0, 0);
     } else {
 #pragma unroll
-        for (int k = 0; k < DPL; ++k) gstore(dst + k, (uint8_t)L[k]);
+        for (int k = 0; k < NW; ++k) __builtin_amdgcn_raw_buffer_store_b8((uint8_t)w[k], rs, off + k, 0, 0);
     }
 }
+
+// store instructions store_path issues per step
+template <int DPL>
+__host__ __device__ constexpr int store_ops()
+{
+    return bytes_per_word<DPL>() == 4 ? (DPL == 12 ? 2 : 1) : DPL / bytes_per_word<DPL>();
+}
+
+// a buffer offset past every buffer: the store is dropped
+constexpr uint32_t kNoStore = 0x80000000u;
+
+// buffer resource word 3 for raw byte buffers (GFX9 family)
+constexpr int kBufferWord3 = 0x00020000;
 
 // s_waitcnt immediate that waits for vmcnt <= n and leaves the other counters
 // alone (GFX9 encoding: vmcnt[3:0] | expcnt[6:4] | lgkmcnt[11:8] | vmcnt_hi[15:14])
@@ -242,13 +292,6 @@ __device__ __forceinline__ void load_u16(const uint16_t *src, uint32_t (&v)[DPL]
             v[2 * i + 1] = w[i] >> 16;
         }
     }
-}
-
-// global store instructions store_bytes issues per step
-template <int DPL>
-__host__ __device__ constexpr int store_ops()
-{
-    return DPL % 4 == 0 ? (DPL == 12 ? 2 : 1) : (DPL % 2 == 0 ? DPL / 2 : DPL);
 }
 
 // Geometry of one block of 16 lines of one direction.
@@ -332,10 +375,11 @@ __device__ __forceinline__ void window_at(const BlockGeom &g, int t, int &row, i
 // dwords (two per word when census words are 64-bit).
 //
 // A kind-2 line that has not started yet (clock < its skew) is fed zero cost:
-// from Q = 0 the recurrence then yields L = 0 and m = 0, so Q stays 0 until the
-// line's first pixel, exactly the state a line starts from.  Lanes of lines that
-// have ended (or not started) store into one spare pixel after the image, so
-// every step issues the same unconditional store.
+// from U = 0 the recurrence then yields U = 0 and u = 0 until the line's first
+// pixel, exactly the state a line starts from.  Lanes of lines that have ended
+// (or not started) pass an offset past the buffer, whose store the hardware
+// drops, so every step issues the same unconditional store (the chunk-end wait
+// counts on that).
 // Census words are read from the LDS tile with inline-assembly ds_read_b32: the
 // tile is filled by direct-to-LDS loads, and for compiler-visible LDS reads the
 // compiler would wait for every outstanding vector memory operation (those loads
@@ -413,7 +457,6 @@ __device__ __forceinline__ void run_lines(const LineArgs &a, const BlockGeom &g,
     uint8_t *__restrict__ out = a.out;
     const uint32_t p1 = a.p1, p2 = a.p2, bits = a.bits;
     const bool padded = D < kDpad;
-    const size_t trash = (size_t)W * H * kDpad + d0;
 
     // per-block line layout
     int row0 = 0, xm0 = 0, xlane = 0, len = 0, skew = 0;
@@ -491,9 +534,14 @@ __device__ __forceinline__ void run_lines(const LineArgs &a, const BlockGeom &g,
         if constexpr (!WIDE) lds_wait<DPL>(wl, wr);
     };
 
-    uint32_t Q[DPL];
+    // un-normalised path sums U of the lane's disparities and the line minimum
+    // u of the previous clock's U
+    uint32_t U[DPL];
 #pragma unroll
-    for (int j = 0; j < DPL; ++j) Q[j] = 0;
+    for (int j = 0; j < DPL; ++j) U[j] = 0;
+    uint32_t u = 0;
+    // a lane's output byte offset moves by this much per clock
+    const int step_off = (HORIZ ? g.dx : g.dy * W + g.dx) * kDpad;
 
     const int nchunks = (g.clocks + kChunk - 1) / kChunk;
     stage(0, 0);
@@ -508,6 +556,21 @@ __device__ __forceinline__ void run_lines(const LineArgs &a, const BlockGeom &g,
         const int c0 = c * kChunk;
         const bool ahead = c + 2 < nchunks;
         if (ahead) stage(c0 + 2 * kChunk, (c + 2) % 3);
+        // the chunk's output window: the image rows its pixels lie in (at most
+        // 16), as a buffer resource, and the lane's byte offset in it at clock c0
+        int rlo, nrows, off;
+        if (HORIZ) {
+            rlo = g.r0;
+            nrows = g.nvalid;
+            off = (li * W + g.xs + c0 * g.dx) * kDpad + d0;
+        } else {
+            const int ra = row0 + c0 * g.dy, rb = row0 + (c0 + kChunk - 1) * g.dy;
+            rlo = max(min(ra, rb), 0);
+            nrows = min(max(ra, rb), H - 1) - rlo + 1;
+            off = ((ra - rlo) * W + xm0 + c0 * g.dx + xlane) * kDpad + d0;
+        }
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(out + (size_t)rlo * W * kDpad, 0, nrows * W * kDpad, kBufferWord3);
         Word wl_n, wr_n[DPL];
         {
             int x, row, xm, slot;
@@ -531,22 +594,23 @@ __device__ __forceinline__ void run_lines(const LineArgs &a, const BlockGeom &g,
                 locate(c0, k + 1, xn, rown, xmn, slotn);
                 fetch(buf, slotn, xn - xmn, wl_n, wr_n);
             }
-            const bool active = s >= 0 && s < len;
-            const uint32_t qm_edge = LO::from_prev(Q[DPL - 1], first);
-            const uint32_t qp_edge = LO::from_next(Q[0], last);
-            uint32_t L[DPL];
-            uint32_t m = 0xFFFFFFFFu;
+            const bool active = (uint32_t)s < (uint32_t)len;
+            const uint32_t um_edge = LO::from_prev(U[DPL - 1], first);
+            const uint32_t up_edge = LO::from_next(U[0], last);
+            const uint32_t cap = u + p2;
+            uint32_t Un[DPL];
+            uint32_t m = kNone;
             // the block's leftmost column decides whether any lane sees x - d < 0;
             // the first chunk of skewed lines has lines that have not started
             const bool border = padded || (HORIZ ? x : xm) < kDpad - 1 || (skewed && c == 0);
             if (!border) {
 #pragma unroll
                 for (int j = 0; j < DPL; ++j) {
-                    const uint32_t qm = j > 0 ? Q[j - 1] : qm_edge;
-                    const uint32_t qp = j < DPL - 1 ? Q[j + 1] : qp_edge;
-                    const uint32_t tt = min(min(Q[j], min(qm, qp) + p1), p2);
-                    L[j] = tt + CW::hamming(wl, wr[DPL - 1 - j]);
-                    m = min(m, L[j]);
+                    const uint32_t um = j > 0 ? U[j - 1] : um_edge;
+                    const uint32_t up = j < DPL - 1 ? U[j + 1] : up_edge;
+                    const uint32_t tt = min(min(U[j], min(um, up) + p1), cap);
+                    Un[j] = tt + CW::hamming(wl, wr[DPL - 1 - j]);
+                    m = min(m, Un[j]);
                 }
             } else {
 #pragma unroll
@@ -554,19 +618,19 @@ __device__ __forceinline__ void run_lines(const LineArgs &a, const BlockGeom &g,
                     const int d = d0 + j;
                     const uint32_t cst = CW::hamming(wl, wr[DPL - 1 - j]);
                     uint32_t C = d < D ? (x - d >= 0 ? cst : bits) : kPadCost;
-                    C = s < 0 ? 0u : C;
-                    const uint32_t qm = j > 0 ? Q[j - 1] : qm_edge;
-                    const uint32_t qp = j < DPL - 1 ? Q[j + 1] : qp_edge;
-                    const uint32_t tt = min(min(Q[j], min(qm, qp) + p1), p2);
-                    L[j] = tt + C;
-                    m = min(m, L[j]);
+                    C = s < 0 ? 0u : C;  // a line that has not started stays at U = 0
+                    const uint32_t um = j > 0 ? U[j - 1] : um_edge;
+                    const uint32_t up = j < DPL - 1 ? U[j + 1] : up_edge;
+                    const uint32_t tt = min(min(U[j], min(um, up) + p1), cap);
+                    Un[j] = tt + C;
+                    m = min(m, Un[j]);
                 }
             }
-            m = LO::line_min(m);
+            store_path<DPL>(rs, active ? (uint32_t)off : kNoStore, Un, u);
+            off += step_off;
+            u = LO::line_min(m);
 #pragma unroll
-            for (int j = 0; j < DPL; ++j) Q[j] = L[j] - m;
-            const size_t o = active ? ((size_t)row * W + x) * kDpad + d0 : trash;
-            store_bytes<DPL>(out + o, L);
+            for (int j = 0; j < DPL; ++j) U[j] = Un[j];
         }
         // the next chunk's tile must have landed: only this chunk's look-ahead
         // loads and its kChunk stores may still be in flight.  The tile is written
