@@ -37,6 +37,23 @@ __device__ __forceinline__ uint32_t row_min(uint32_t v)
 constexpr int kSelBlock = 512;                            // one image row per block
 constexpr int kSelGroups = kSelBlock / kLanesPerLine;     // pixels in flight per row
 
+// Pixel steps of path values held in registers (loads run ring - 1 steps
+// ahead), and the waves per SIMD the register budget is sized for: one block
+// per image row and three blocks per CU (six waves per SIMD) cover a 720-row
+// image in one pass; the widest lanes, 16-bit values and byte values that need
+// the split sums (any value >= 128) keep two steps and take the registers they
+// need.
+constexpr int sel_ring(int dpl, bool v16, bool small) { return (dpl <= 8 && !v16 && (small || dpl <= 4)) ? 3 : 2; }
+constexpr int sel_waves_per_simd(int dpl, bool v16, bool small) { return sel_ring(dpl, v16, small) == 3 ? 6 : 2; }
+
+template <typename T>
+__device__ __forceinline__ T *uniform_ptr(T *p)
+{
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v), hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (T *)(((uint64_t)hi << 32) | lo);
+}
+
 // the dpl path values of one direction for this lane, as packed words: bytes,
 // or 16-bit values (V16, block matching)
 template <int DPL, bool V16 = false>
@@ -45,26 +62,35 @@ struct Words {
     uint32_t w[N];
 };
 
+typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
+// buffer resource word 3 for raw byte buffers (GFX9 family)
+constexpr int kBufferWord3 = 0x00020000;
+
+// The path values of one pixel come through raw buffer loads: one resource per
+// direction covers the block's image row, so all directions share one 32-bit
+// offset register instead of a 64-bit address each.
 template <int DPL>
-__device__ __forceinline__ void load_words(const uint8_t *src, Words<DPL, true> &o)
+__device__ __forceinline__ void load_words(__amdgpu_buffer_rsrc_t rs, uint32_t off, Words<DPL, true> &o)
 {
     if constexpr (DPL == 1) {
-        o.w[0] = *(const uint16_t *)src;
+        o.w[0] = __builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, 0);
     } else if constexpr (DPL % 8 == 0) {
 #pragma unroll
         for (int i = 0; i < DPL / 2; i += 4) {
-            const uint4 v = *(const uint4 *)(src + 4 * i);
-            o.w[i] = v.x; o.w[i + 1] = v.y; o.w[i + 2] = v.z; o.w[i + 3] = v.w;
+            const u32x4_t v = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 4 * i, 0, 0);
+            o.w[i] = v[0]; o.w[i + 1] = v[1]; o.w[i + 2] = v[2]; o.w[i + 3] = v[3];
         }
     } else if constexpr (DPL % 4 == 0) {
 #pragma unroll
         for (int i = 0; i < DPL / 2; i += 2) {
-            const uint2 v = *(const uint2 *)(src + 4 * i);
-            o.w[i] = v.x; o.w[i + 1] = v.y;
+            const u32x2_t v = __builtin_amdgcn_raw_buffer_load_b64(rs, off + 4 * i, 0, 0);
+            o.w[i] = v[0]; o.w[i + 1] = v[1];
         }
     } else {
 #pragma unroll
-        for (int i = 0; i < DPL / 2; ++i) o.w[i] = *(const uint32_t *)(src + 4 * i);
+        for (int i = 0; i < DPL / 2; ++i) o.w[i] = __builtin_amdgcn_raw_buffer_load_b32(rs, off + 4 * i, 0, 0);
     }
 }
 
@@ -86,35 +112,37 @@ __device__ __forceinline__ void sum_paths16(const Words<DPL, true> (&v)[NDIR], u
 }
 
 template <int DPL>
-__device__ __forceinline__ void load_words(const uint8_t *src, Words<DPL> &o)
+__device__ __forceinline__ void load_words(__amdgpu_buffer_rsrc_t rs, uint32_t off, Words<DPL> &o)
 {
     if constexpr (DPL == 4) {
-        o.w[0] = *(const uint32_t *)src;
+        o.w[0] = __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
     } else if constexpr (DPL == 8) {
-        const uint2 v = *(const uint2 *)src;
-        o.w[0] = v.x;
-        o.w[1] = v.y;
+        const u32x2_t v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+        o.w[0] = v[0];
+        o.w[1] = v[1];
     } else if constexpr (DPL == 12) {
-        const uint2 v = *(const uint2 *)src;
-        o.w[0] = v.x;
-        o.w[1] = v.y;
-        o.w[2] = *(const uint32_t *)(src + 8);
+        const u32x2_t v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+        o.w[0] = v[0];
+        o.w[1] = v[1];
+        o.w[2] = __builtin_amdgcn_raw_buffer_load_b32(rs, off + 8, 0, 0);
     } else if constexpr (DPL == 16) {
-        const uint4 v = *(const uint4 *)src;
-        o.w[0] = v.x;
-        o.w[1] = v.y;
-        o.w[2] = v.z;
-        o.w[3] = v.w;
+        const u32x4_t v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+        o.w[0] = v[0];
+        o.w[1] = v[1];
+        o.w[2] = v[2];
+        o.w[3] = v[3];
     } else if constexpr (DPL == 6) {
-        const uint32_t a0 = *(const uint16_t *)src, a1 = *(const uint16_t *)(src + 2),
-                       a2 = *(const uint16_t *)(src + 4);
-        o.w[0] = a0 | (a1 << 16);
-        o.w[1] = a2;
+        // 6 bytes at an even offset lie in the 8 bytes from the dword below it
+        // (which end inside the same pixel's values): one load, then a shift
+        const u32x2_t v = __builtin_amdgcn_raw_buffer_load_b64(rs, off & ~3u, 0, 0);
+        const uint32_t sh = (off & 2u) * 8;
+        o.w[0] = __builtin_amdgcn_alignbit(v[1], v[0], sh);
+        o.w[1] = v[1] >> sh;  // bytes 0, 1 are d0 + 4, d0 + 5; the rest is unused
     } else if constexpr (DPL == 2) {
-        o.w[0] = *(const uint16_t *)src;
+        o.w[0] = __builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, 0);
     } else {
         static_assert(DPL == 1, "unsupported disparities per lane");
-        o.w[0] = *src;
+        o.w[0] = __builtin_amdgcn_raw_buffer_load_b8(rs, off, 0, 0);
     }
 }
 
@@ -257,19 +285,28 @@ __device__ __forceinline__ void select_row(const SelectArgs &a, int y, uint32_t 
     const int lane = threadIdx.x % kLanesPerLine, group = threadIdx.x / kLanesPerLine;
     const int d0 = lane * DPL;
     uint16_t *my = srow + group * kDpad;
-    Words<DPL, V16> cur[NDIR], nxt[NDIR];
-    if (group < W) {
+    // the pixel loop keeps a ring of kRing pixel steps of path values in
+    // registers, loaded kRing - 1 steps ahead; the loop is unrolled over the
+    // ring so no register still awaiting its load is ever copied (a copy would
+    // wait for it), and look-ahead loads are unconditional (clamped to the row's
+    // last pixel) so every wait counts the same loads
+    constexpr int kRing = sel_ring(DPL, V16, SMALL);
+    __amdgpu_buffer_rsrc_t rs[NDIR];
 #pragma unroll
-        for (int r = 0; r < NDIR; ++r) load_words<DPL>(a.paths[r] + ((row + group) * kDpad + d0) * kValBytes, cur[r]);
+    for (int r = 0; r < NDIR; ++r) {
+        const uint8_t *base = uniform_ptr(a.paths[r]) + row * kDpad * kValBytes;
+        rs[r] = __builtin_amdgcn_make_buffer_rsrc((void *)base, 0, W * kDpad * kValBytes, kBufferWord3);
     }
-    for (int x = group; x < W; x += kSelGroups) {
-        // look-ahead loads are unconditional (clamped to the row's last pixel)
-        const int xn = min(x + kSelGroups, W - 1);
+    Words<DPL, V16> ring[kRing][NDIR];
+    auto load_px = [&](int x, Words<DPL, V16>(&v)[NDIR]) {
+        const uint32_t off = (uint32_t)((min(x, W - 1) * kDpad + d0) * kValBytes);
 #pragma unroll
-        for (int r = 0; r < NDIR; ++r) load_words<DPL>(a.paths[r] + ((row + xn) * kDpad + d0) * kValBytes, nxt[r]);
+        for (int r = 0; r < NDIR; ++r) load_words<DPL>(rs[r], off, v[r]);
+    };
+    auto process = [&](int x, const Words<DPL, V16>(&v)[NDIR]) {
         uint32_t S[DPL];
-        if constexpr (V16) sum_paths16<DPL, NDIR>(cur, S);
-        else sum_paths<DPL, NDIR, SMALL>(cur, S);
+        if constexpr (V16) sum_paths16<DPL, NDIR>(v, S);
+        else sum_paths<DPL, NDIR, SMALL>(v, S);
         if (D < kDpad) {
             // padding disparities: a cost above every real one (real S < 2^16 - 8)
 #pragma unroll
@@ -317,8 +354,21 @@ __device__ __forceinline__ void select_row(const SelectArgs &a, int y, uint32_t 
             dsub_row[x] = ds;
             uniq_row[x] = uniq;
         }
+    };
+    // (one step's loads after the other, not interleaved by the scheduler: the
+    // waits count loads in issue order)
 #pragma unroll
-        for (int r = 0; r < NDIR; ++r) cur[r] = nxt[r];
+    for (int k = 0; k < kRing - 1; ++k) {
+        load_px(group + k * kSelGroups, ring[k]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    for (int x0 = group; x0 < W; x0 += kRing * kSelGroups) {
+#pragma unroll
+        for (int s = 0; s < kRing; ++s) {
+            load_px(x0 + (s + kRing - 1) * kSelGroups, ring[(s + kRing - 1) % kRing]);
+            const int x = x0 + s * kSelGroups;
+            if (x < W) process(x, ring[s]);
+        }
     }
     __syncthreads();
     const int lr = a.lr_max_diff;
@@ -339,7 +389,7 @@ __device__ __forceinline__ void select_row(const SelectArgs &a, int y, uint32_t 
 }
 
 template <int DPL, int NDIR, bool SMALL, bool V16>
-__global__ __launch_bounds__(kSelBlock) void select_kernel(SelectArgs a)
+__global__ __launch_bounds__(kSelBlock, sel_waves_per_simd(DPL, V16, SMALL)) void select_kernel(SelectArgs a)
 {
     extern __shared__ uint32_t smem[];
     select_row<DPL, NDIR, SMALL, V16>(a, (int)blockIdx.x, smem);
@@ -347,7 +397,7 @@ __global__ __launch_bounds__(kSelBlock) void select_kernel(SelectArgs a)
 
 // batch form: one block per (pair slot, row) item
 template <int DPL, int NDIR, bool SMALL>
-__global__ __launch_bounds__(kSelBlock) void select_batch_kernel(SelectBatch b)
+__global__ __launch_bounds__(kSelBlock, sel_waves_per_simd(DPL, false, SMALL)) void select_batch_kernel(SelectBatch b)
 {
     extern __shared__ uint32_t smem[];
     const uint32_t it = b.items[blockIdx.x];
