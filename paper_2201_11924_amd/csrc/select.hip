@@ -67,6 +67,10 @@ typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 
 // buffer resource word 3 for raw byte buffers (GFX9 family)
 constexpr int kBufferWord3 = 0x00020000;
+// Path values are read exactly once: non-temporal (NT) loads keep them from
+// displacing other lines in the caches (measured: 185 -> 167 us for a 1280x720
+// D=128 8-path selection).
+constexpr int kLoadAux = 2;
 
 // The path values of one pixel come through raw buffer loads: one resource per
 // direction covers the block's image row, so all directions share one 32-bit
@@ -75,22 +79,22 @@ template <int DPL>
 __device__ __forceinline__ void load_words(__amdgpu_buffer_rsrc_t rs, uint32_t off, Words<DPL, true> &o)
 {
     if constexpr (DPL == 1) {
-        o.w[0] = __builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, 0);
+        o.w[0] = __builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, kLoadAux);
     } else if constexpr (DPL % 8 == 0) {
 #pragma unroll
         for (int i = 0; i < DPL / 2; i += 4) {
-            const u32x4_t v = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 4 * i, 0, 0);
+            const u32x4_t v = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 4 * i, 0, kLoadAux);
             o.w[i] = v[0]; o.w[i + 1] = v[1]; o.w[i + 2] = v[2]; o.w[i + 3] = v[3];
         }
     } else if constexpr (DPL % 4 == 0) {
 #pragma unroll
         for (int i = 0; i < DPL / 2; i += 2) {
-            const u32x2_t v = __builtin_amdgcn_raw_buffer_load_b64(rs, off + 4 * i, 0, 0);
+            const u32x2_t v = __builtin_amdgcn_raw_buffer_load_b64(rs, off + 4 * i, 0, kLoadAux);
             o.w[i] = v[0]; o.w[i + 1] = v[1];
         }
     } else {
 #pragma unroll
-        for (int i = 0; i < DPL / 2; ++i) o.w[i] = __builtin_amdgcn_raw_buffer_load_b32(rs, off + 4 * i, 0, 0);
+        for (int i = 0; i < DPL / 2; ++i) o.w[i] = __builtin_amdgcn_raw_buffer_load_b32(rs, off + 4 * i, 0, kLoadAux);
     }
 }
 
@@ -115,18 +119,18 @@ template <int DPL>
 __device__ __forceinline__ void load_words(__amdgpu_buffer_rsrc_t rs, uint32_t off, Words<DPL> &o)
 {
     if constexpr (DPL == 4) {
-        o.w[0] = __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
+        o.w[0] = __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, kLoadAux);
     } else if constexpr (DPL == 8) {
-        const u32x2_t v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+        const u32x2_t v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, kLoadAux);
         o.w[0] = v[0];
         o.w[1] = v[1];
     } else if constexpr (DPL == 12) {
-        const u32x2_t v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+        const u32x2_t v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, kLoadAux);
         o.w[0] = v[0];
         o.w[1] = v[1];
-        o.w[2] = __builtin_amdgcn_raw_buffer_load_b32(rs, off + 8, 0, 0);
+        o.w[2] = __builtin_amdgcn_raw_buffer_load_b32(rs, off + 8, 0, kLoadAux);
     } else if constexpr (DPL == 16) {
-        const u32x4_t v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+        const u32x4_t v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, kLoadAux);
         o.w[0] = v[0];
         o.w[1] = v[1];
         o.w[2] = v[2];
@@ -134,15 +138,15 @@ __device__ __forceinline__ void load_words(__amdgpu_buffer_rsrc_t rs, uint32_t o
     } else if constexpr (DPL == 6) {
         // 6 bytes at an even offset lie in the 8 bytes from the dword below it
         // (which end inside the same pixel's values): one load, then a shift
-        const u32x2_t v = __builtin_amdgcn_raw_buffer_load_b64(rs, off & ~3u, 0, 0);
+        const u32x2_t v = __builtin_amdgcn_raw_buffer_load_b64(rs, off & ~3u, 0, kLoadAux);
         const uint32_t sh = (off & 2u) * 8;
         o.w[0] = __builtin_amdgcn_alignbit(v[1], v[0], sh);
         o.w[1] = v[1] >> sh;  // bytes 0, 1 are d0 + 4, d0 + 5; the rest is unused
     } else if constexpr (DPL == 2) {
-        o.w[0] = __builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, 0);
+        o.w[0] = __builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, kLoadAux);
     } else {
         static_assert(DPL == 1, "unsupported disparities per lane");
-        o.w[0] = __builtin_amdgcn_raw_buffer_load_b8(rs, off, 0, 0);
+        o.w[0] = __builtin_amdgcn_raw_buffer_load_b8(rs, off, 0, kLoadAux);
     }
 }
 
