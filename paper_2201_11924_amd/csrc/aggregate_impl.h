@@ -38,6 +38,8 @@
 // buffer of its own, d fastest; the selection pass sums the directions.
 #pragma once
 #include <algorithm>
+#include <type_traits>
+#include <utility>
 
 #include "internal.h"
 
@@ -403,13 +405,26 @@ __device__ __forceinline__ uint32_t ds_read_at(uint32_t addr)
     return v;
 }
 
-template <int N, int J = 0>
+template <int N, int BASE = 0, int J = 0>
 __device__ __forceinline__ void ds_read_run(uint32_t addr, uint32_t (&w)[N])
 {
     if constexpr (J < N) {
-        w[J] = ds_read_at<4 * J>(addr);
-        ds_read_run<N, J + 1>(addr, w);
+        w[J] = ds_read_at<BASE + 4 * J>(addr);
+        ds_read_run<N, BASE, J + 1>(addr, w);
     }
+}
+
+// f(integral_constant<int, 0>), ..., f(integral_constant<int, N - 1>): a loop
+// whose index is a constant expression in the body (LDS offsets as immediates)
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, I...>)
+{
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
 template <int N>
@@ -579,14 +594,30 @@ __device__ __forceinline__ void run_lines(const LineArgs &a, const BlockGeom &g,
         }
         const __amdgpu_buffer_rsrc_t rs =
             __builtin_amdgcn_make_buffer_rsrc(out + (size_t)rlo * W * kDpad, 0, nrows * W * kDpad, kBufferWord3);
-        Word wl_n, wr_n[DPL];
-        {
-            int x, row, xm, slot;
-            locate(c0, 0, x, row, xm, slot);
-            fetch(buf, slot, x - xm, wl_n, wr_n);
+        // census words of clock K of the chunk.  Lines sharing an image row read
+        // tile slot K at a fixed column of the lane, so the LDS addresses are two
+        // per-chunk registers plus immediate offsets.
+        uint32_t aL = 0, aR = 0;
+        if constexpr (!HORIZ && !WIDE) {
+            const uint32_t tb = lds_addr(&tile[buf][0]);
+            aL = tb + (uint32_t)(kDpad + kChunk - 1 + xlane) * 4;
+            aR = tb + (uint32_t)(xlane + kDpad - d0 - DPL) * 4;
         }
-#pragma unroll
-        for (int k = 0; k < kChunk; ++k) {
+        auto fetch_clock = [&](auto kc, Word &wl, Word(&wr)[DPL]) {
+            constexpr int K = decltype(kc)::value;
+            if constexpr (!HORIZ && !WIDE) {
+                wl = ds_read_at<K * kSlot * 4>(aL);
+                ds_read_run<DPL, K * kSlot * 4>(aR, wr);
+            } else {
+                int x, row, xm, slot;
+                locate(c0, K, x, row, xm, slot);
+                fetch(buf, slot, x - xm, wl, wr);
+            }
+        };
+        Word wl_n, wr_n[DPL];
+        fetch_clock(std::integral_constant<int, 0>{}, wl_n, wr_n);
+        static_for<kChunk>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
             const int t = c0 + k;
             const int s = t - skew;
             int x, row, xm, slot;
@@ -596,13 +627,11 @@ __device__ __forceinline__ void run_lines(const LineArgs &a, const BlockGeom &g,
             Word wr[DPL];
 #pragma unroll
             for (int j = 0; j < DPL; ++j) wr[j] = wr_n[j];
-            if (k + 1 < kChunk) {
-                // next clock's census words are read while this clock computes
-                int xn, rown, xmn, slotn;
-                locate(c0, k + 1, xn, rown, xmn, slotn);
-                fetch(buf, slotn, xn - xmn, wl_n, wr_n);
-            }
-            const bool active = (uint32_t)s < (uint32_t)len;
+            // next clock's census words are read while this clock computes
+            if constexpr (k + 1 < kChunk) fetch_clock(std::integral_constant<int, k + 1>{}, wl_n, wr_n);
+            // (horizontal lines all span the image width: a per-lane constant and a
+            // uniform test, so the check stays on the scalar unit)
+            const bool active = HORIZ ? (len > 0 && t < W) : (uint32_t)s < (uint32_t)len;
             const uint32_t um_edge = LO::from_prev(U[DPL - 1], first);
             const uint32_t up_edge = LO::from_next(U[0], last);
             const uint32_t cap = u + p2;
@@ -639,7 +668,7 @@ __device__ __forceinline__ void run_lines(const LineArgs &a, const BlockGeom &g,
             u = LO::line_min(m);
 #pragma unroll
             for (int j = 0; j < DPL; ++j) U[j] = Un[j];
-        }
+        });
         // the next chunk's tile must have landed: only this chunk's look-ahead
         // loads and its kChunk stores may still be in flight.  The tile is written
         // by the loads themselves, so a bare s_barrier (no release fence, which
