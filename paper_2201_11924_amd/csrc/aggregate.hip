@@ -66,6 +66,12 @@ int aggregate_block_clocks(int dx, int dy, int blk, int W, int H, int hl)
     return c;
 }
 
+int aggregate_block_work(int dx, int dy, int blk, int W, int H, int hl, int dpad)
+{
+    const int cost = dy == 0 ? agg_step_cost(dpad / hl, hl) : agg_step_cost(dpad / kLanesPerLine, kLanesPerLine);
+    return aggregate_block_clocks(dx, dy, blk, W, H, hl) * cost;
+}
+
 namespace {
 __global__ void zero_counters_kernel(unsigned *c, int n)
 {

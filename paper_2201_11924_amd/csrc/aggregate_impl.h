@@ -444,6 +444,7 @@ struct LineArgs {
     const uint32_t *cl, *cr;  // census words (dwords; two per word when 64-bit)
     uint8_t *out;             // this direction's path values
     int W, H, D, p1, p2, bits;
+    int max_work;             // largest block work of the launch (agg_step_cost units)
 };
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -578,6 +579,18 @@ __device__ __forceinline__ void run_lines(const LineArgs &a, const BlockGeom &g,
         const int buf = c % 3;
         const int c0 = c * kChunk;
         const bool ahead = c + 2 < nchunks;
+        {
+            // issue priority from the block's remaining work relative to the
+            // launch's largest block: the blocks sharing a SIMD then drain in
+            // order of remaining work and tend to finish together, instead of the
+            // last one running on alone (measured: 8-path 1280x720 D=128 pass
+            // 386 -> 357 us)
+            const int rem100 = (g.clocks - c0) * agg_step_cost(DPL, LPL) * 100;
+            if (rem100 > 43 * a.max_work) __builtin_amdgcn_s_setprio(3);
+            else if (rem100 > 21 * a.max_work) __builtin_amdgcn_s_setprio(2);
+            else if (rem100 > 7 * a.max_work) __builtin_amdgcn_s_setprio(1);
+            else __builtin_amdgcn_s_setprio(0);
+        }
         if (ahead) stage(c0 + 2 * kChunk, (c + 2) % 3);
         // the chunk's output window: the image rows its pixels lie in (at most
         // 16), as a buffer resource, and the lane's byte offset in it at clock c0
@@ -710,17 +723,16 @@ __device__ __forceinline__ void aggregate_block(const AggregateArgs &a, int blk,
     la.out = uniform(a.out[dir]);
     la.W = uniform(a.W); la.H = uniform(a.H); la.D = uniform(a.D);
     la.p1 = uniform(a.p1); la.p2 = uniform(a.p2); la.bits = uniform(a.bits);
+    la.max_work = uniform(max(a.max_item_work, 1));
     const BlockGeom g = block_geometry(uniform(a.dx[dir]), uniform(a.dy[dir]), blk - uniform(a.block_begin[dir]),
                                        la.W, la.H, kBlock / HL);
     if (g.kind == 0) {
-        // horizontal lines are the longest dependency chains of the pass: more
-        // lanes per line to shorten each step, and issue priority
-        __builtin_amdgcn_s_setprio(2);
+        // horizontal lines: more lanes per line to shorten each step
         run_lines<kDpad / HL, HL, WIDE, true, agg_tile_dwords<DPL, WIDE>()>(la, g, tile);
-        __builtin_amdgcn_s_setprio(0);
     } else {
         run_lines<DPL, kLanesPerLine, WIDE, false, agg_tile_dwords<DPL, WIDE>()>(la, g, tile);
     }
+    __builtin_amdgcn_s_setprio(0);
 }
 
 template <int DPL, bool WIDE, int HL>

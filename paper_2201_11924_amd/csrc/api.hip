@@ -166,6 +166,9 @@ static AggregateArgs handle_aggregate_args(const simsense_handle *h)
         ag.dy[r] = kPathDy[r];
         ag.out[r] = h->paths[r];
         ag.block_begin[r + 1] = ag.block_begin[r] + aggregate_blocks(kPathDx[r], kPathDy[r], p.width, p.height, h->hlanes);
+        for (int k = 0; k < ag.block_begin[r + 1] - ag.block_begin[r]; ++k)
+            ag.max_item_work = std::max(ag.max_item_work, aggregate_block_work(kPathDx[r], kPathDy[r], k, p.width,
+                                                                               p.height, h->hlanes, h->Dpad));
     }
     return ag;
 }
@@ -223,7 +226,8 @@ static int sgbm_aggregation(simsense_handle *h, const void *cl, const void *cr, 
 }
 
 // Applies a tuning: lane count, and for the persistent form the work list of
-// line blocks sorted longest first (stable, so equal lengths keep direction order).
+// line blocks sorted by estimated work, largest first (stable, so equal work
+// keeps direction order).
 static int apply_tuning(simsense_handle *h, const simsense_batch_tuning &t)
 {
     const int hl = t.horizontal_lanes == 0 ? horizontal_lanes(h->Dpad) : t.horizontal_lanes;
@@ -234,7 +238,7 @@ static int apply_tuning(simsense_handle *h, const simsense_batch_tuning &t)
     std::vector<std::pair<int, uint32_t>> lst;
     for (int r = 0; r < h->ndirs; ++r)
         for (int k = 0; k < ag.block_begin[r + 1] - ag.block_begin[r]; ++k)
-            lst.push_back({aggregate_block_clocks(kPathDx[r], kPathDy[r], k, h->p.width, h->p.height, hl),
+            lst.push_back({aggregate_block_work(kPathDx[r], kPathDy[r], k, h->p.width, h->p.height, hl, h->Dpad),
                            (uint32_t)(ag.block_begin[r] + k)});
     std::stable_sort(lst.begin(), lst.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
     std::vector<uint32_t> items(lst.size());

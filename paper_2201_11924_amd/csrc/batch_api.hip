@@ -106,7 +106,7 @@ int build_plan(simsense_batch *b)
             for (int i = 0; i < t; ++i) items.push_back(((uint32_t)(2 * s + img) << 20) | (uint32_t)i);
     }
     b->census_nitems = (int)(items.size() - b->census_item_off);
-    // aggregation: group slots by (Dpad, wide); items longest first
+    // aggregation: group slots by (Dpad, wide); items largest estimated work first
     std::vector<AggregateArgs> agg(n);
     std::map<std::pair<int, bool>, std::vector<std::pair<int, uint32_t>>> groups;
     for (int s = 0; s < n; ++s) {
@@ -127,8 +127,8 @@ int build_plan(simsense_batch *b)
             a.out[r] = b->scratch + sl.off_paths[r];
             const int nb = aggregate_blocks(kPathDx[r], kPathDy[r], a.W, a.H, sl.hl);
             for (int k = 0; k < nb; ++k) {
-                const int clocks = aggregate_block_clocks(kPathDx[r], kPathDy[r], k, a.W, a.H, sl.hl);
-                lst.push_back({clocks, ((uint32_t)s << 20) | (uint32_t)(a.block_begin[r] + k)});
+                const int work = aggregate_block_work(kPathDx[r], kPathDy[r], k, a.W, a.H, sl.hl, sl.Dpad);
+                lst.push_back({work, ((uint32_t)s << 20) | (uint32_t)(a.block_begin[r] + k)});
             }
             a.block_begin[r + 1] = a.block_begin[r] + nb;
         }
@@ -137,6 +137,10 @@ int build_plan(simsense_batch *b)
     for (auto &kv : groups) {
         auto &lst = kv.second;
         std::stable_sort(lst.begin(), lst.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
+        // the group's blocks run in one launch: its largest block sets the scale
+        // of every slot's issue priorities
+        const int gmax = lst.empty() ? 0 : lst.front().first;
+        for (auto &e : lst) agg[e.second >> 20].max_item_work = gmax;
         simsense_batch::AggGroup gr{};
         gr.dpad = kv.first.first;
         gr.wide = kv.first.second;

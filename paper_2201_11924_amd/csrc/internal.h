@@ -33,6 +33,11 @@ bool horizontal_lanes_valid(int dpad, int hl);
 // blocks of work of one direction, and the clocks block `blk` runs
 int aggregate_blocks(int dx, int dy, int W, int H, int hl);
 int aggregate_block_clocks(int dx, int dy, int blk, int W, int H, int hl);
+// Estimated VALU instructions per clock of a wave of a line block: about 7 per
+// disparity a lane holds, plus the per-step line overhead (larger for lines
+// spread over more than one DPP row).  The work of a block is clocks x this.
+constexpr int agg_step_cost(int dpl, int lanes_per_line) { return 7 * dpl + (lanes_per_line == 16 ? 10 : 18); }
+int aggregate_block_work(int dx, int dy, int blk, int W, int H, int hl, int dpad);
 
 struct AggregateArgs {
     const void *census_l, *census_r;  // uint32 words, or uint64 when bits > 32
@@ -41,6 +46,7 @@ struct AggregateArgs {
     int dx[8], dy[8];
     int block_begin[9];  // first block index of each direction, prefix sums
     uint8_t *out[8];     // per-direction path values, W*H*Dpad bytes, d fastest
+    int max_item_work;   // largest block work of the launch (issue priorities)
 };
 
 struct SelectArgs {
