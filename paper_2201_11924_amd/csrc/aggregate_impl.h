@@ -481,6 +481,8 @@ __device__ __forceinline__ void run_lines(const LineArgs &a, const BlockGeom &g,
     uint8_t *__restrict__ out = a.out;
     const uint32_t p1 = a.p1, p2 = a.p2, bits = a.bits;
     const bool padded = D < kDpad;
+    // the census bits of a word (a word XORed with this differs from it in `bits` bits)
+    const Word bits_mask = bits >= 8 * sizeof(Word) ? ~(Word)0 : (((Word)1 << bits) - 1);
 
     // per-block line layout
     int row0 = 0, xm0 = 0, xlane = 0, len = 0, skew = 0;
@@ -652,7 +654,8 @@ __device__ __forceinline__ void run_lines(const LineArgs &a, const BlockGeom &g,
             uint32_t m = kNone;
             // the block's leftmost column decides whether any lane sees x - d < 0;
             // the first chunk of skewed lines has lines that have not started
-            const bool border = padded || (HORIZ ? x : xm) < kDpad - 1 || (skewed && c == 0);
+            const bool clip = (HORIZ ? x : xm) < kDpad - 1;
+            const bool border = padded || clip || (skewed && c == 0);
             if (!border) {
 #pragma unroll
                 for (int j = 0; j < DPL; ++j) {
@@ -660,6 +663,21 @@ __device__ __forceinline__ void run_lines(const LineArgs &a, const BlockGeom &g,
                     const uint32_t up = j < DPL - 1 ? U[j + 1] : up_edge;
                     const uint32_t tt = min(min(U[j], min(um, up) + p1), cap);
                     Un[j] = tt + CW::hamming(wl, wr[DPL - 1 - j]);
+                    m = min(m, Un[j]);
+                }
+            } else if (!padded && !(skewed && c == 0)) {
+                // only x - d < 0 occurs: those disparities compare cL with a word at
+                // Hamming distance `bits` from it (cL ^ mask), which costs exactly
+                // `bits`, so the update keeps its fused form
+                const Word wfix = wl ^ bits_mask;
+                const int xd = x - d0;
+#pragma unroll
+                for (int j = 0; j < DPL; ++j) {
+                    const Word wrj = j <= xd ? wr[DPL - 1 - j] : wfix;
+                    const uint32_t um = j > 0 ? U[j - 1] : um_edge;
+                    const uint32_t up = j < DPL - 1 ? U[j + 1] : up_edge;
+                    const uint32_t tt = min(min(U[j], min(um, up) + p1), cap);
+                    Un[j] = tt + CW::hamming(wl, wrj);
                     m = min(m, Un[j]);
                 }
             } else {
