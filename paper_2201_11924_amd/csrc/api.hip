@@ -257,7 +257,7 @@ static int apply_tuning(simsense_handle *h, const simsense_batch_tuning &t)
 }
 
 int enqueue_match(simsense_handle *h, const uint8_t *left, const uint8_t *right, int pitch, hipStream_t s,
-                  uint16_t *volume_out)
+                  uint16_t *volume_out, bool need_right)
 {
     const simsense_params &p = h->p;
     const int W = p.width, H = p.height, D = p.max_disp;
@@ -304,6 +304,7 @@ int enqueue_match(simsense_handle *h, const uint8_t *left, const uint8_t *right,
     sa.small_values = !h->sgbm && h->bits + p.p2 <= 127;
     sa.disp_int = h->disp_int; sa.cost_best = h->cost_best; sa.cost_second = h->cost_second;
     sa.disp_right = h->disp_right; sa.disp_sub = h->disp_sub; sa.masked = h->masked; sa.flags = h->flags_pre;
+    sa.no_right = !need_right;
     profile_mark(h, SIMSENSE_PASS_SELECT, false, s);
     SS_TRY(launch_select(sa, s));
     if (p.lr_mode == 1) {

@@ -209,7 +209,7 @@ __global__ void zero_words(unsigned *c, int n)
 }
 
 // census, aggregation and selection of every slot
-int enqueue_match_batch(simsense_batch *b, hipStream_t s)
+int enqueue_match_batch(simsense_batch *b, hipStream_t s, bool need_right = true)
 {
     const int ngroups = (int)b->agg_groups.size();
     if (ngroups > 0) B_TRY(launch_zero_counters(b->d_counters, ngroups, s));
@@ -235,6 +235,7 @@ int enqueue_match_batch(simsense_batch *b, hipStream_t s)
         sb.items = b->d_items + g.item_off;
         sb.nitems = g.nitems;
         sb.max_width = b->max_w;
+        sb.no_right = !need_right;
         B_TRY(launch_select_batch(sb, g.dpad, g.ndirs, g.small, s));
     }
     return SIMSENSE_OK;
@@ -263,7 +264,8 @@ int enqueue_learned_batch(simsense_batch *b, simsense_net *net, float tau, unsig
 {
     hipLaunchKernelGGL(zero_words, dim3(1), dim3(256), 0, s, uncertain, b->n);
     B_TRY(hipGetLastError());
-    int rc = enqueue_match_batch(b, s);
+    // the learned form reads d*, S1, S2 and the sub-pixel disparity only
+    int rc = enqueue_match_batch(b, s, /*need_right=*/false);
     if (rc != SIMSENSE_OK) return rc;
     const Slot &s0 = b->slots[0];
     const int W = s0.p.width, H = s0.p.height;

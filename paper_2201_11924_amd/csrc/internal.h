@@ -63,6 +63,7 @@ struct SelectArgs {
     float *disp_sub;      // before masking
     float *masked;        // masked sub-pixel disparity (0 = invalid)
     uint8_t *flags;       // bits 0..2
+    int no_right;         // skip the right-image disparity (no LR check, disp_right unwritten)
 };
 
 struct PostArgs {
@@ -140,6 +141,7 @@ struct SelectBatch {
     const SelectArgs *slots;
     const uint32_t *items;  // slot << 20 | row
     int nitems, max_width;
+    int no_right;           // as SelectArgs::no_right, for every slot of the launch
 };
 struct PostBatch {
     const PostArgs *slots;
@@ -162,8 +164,10 @@ hipError_t launch_volume_sum(const PathSet &paths, int ndirs, bool values16, int
 //                 (d*, S1, S2, dR, sub-pixel, masked disparity, flags bits 0..2);
 //  enqueue_post:  median + depth of a masked map into the caller's outputs.
 //                 (volume_out, if set, receives the summed path costs S)
+//                 (need_right = false: the learned form, which reads only d*, S1,
+//                 S2 and the sub-pixel disparity, skips the right-image disparity)
 int enqueue_match(simsense_handle *h, const uint8_t *left, const uint8_t *right, int pitch, hipStream_t s,
-                  uint16_t *volume_out = nullptr);
+                  uint16_t *volume_out = nullptr, bool need_right = true);
 int enqueue_post(simsense_handle *h, const float *masked, const uint8_t *flags_pre, const simsense_outputs *o,
                  hipStream_t s);
 int profile_begin_call(simsense_handle *h);

@@ -376,7 +376,7 @@ int simsense_learned_compute(simsense_handle *h, simsense_net *n, const uint8_t 
     const int64_t P = (int64_t)p.width * p.height;
     int rc = profile_begin_call(h);
     if (rc != SIMSENSE_OK) return rc;
-    rc = enqueue_match(h, left, right, pitch, s);
+    rc = enqueue_match(h, left, right, pitch, s, nullptr, /*need_right=*/false);
     if (rc != SIMSENSE_OK) return rc;
     FeatureArgs fa{};
     fa.ir = left; fa.pitch = pitch; fa.W = p.width;

@@ -266,7 +266,7 @@ constexpr size_t select_lds_bytes(int W)
 }
 
 template <int DPL, int NDIR, bool SMALL, bool V16 = false>
-__device__ __forceinline__ void select_row(const SelectArgs &a, int y, uint32_t *smem)
+__device__ __forceinline__ void select_row(const SelectArgs &a, int y, uint32_t *smem, bool right)
 {
     constexpr int kValBytes = V16 ? 2 : 1;
     constexpr int kDpad = kLanesPerLine * DPL;
@@ -283,7 +283,8 @@ __device__ __forceinline__ void select_row(const SelectArgs &a, int y, uint32_t 
     uint8_t *dint_row = (uint8_t *)(s2_row + W);
     uint8_t *uniq_row = dint_row + W;
     const size_t row = (size_t)y * W;
-    for (int i = threadIdx.x; i < kDpad + W; i += kSelBlock) keyR[i] = 0xFFFFFFFFu;
+    if (right)
+        for (int i = threadIdx.x; i < kDpad + W; i += kSelBlock) keyR[i] = 0xFFFFFFFFu;
     __syncthreads();
 
     const int lane = threadIdx.x % kLanesPerLine, group = threadIdx.x / kLanesPerLine;
@@ -323,10 +324,10 @@ __device__ __forceinline__ void select_row(const SelectArgs &a, int y, uint32_t 
         uint32_t kmin = 0xFFFFFFFFu;
         const int kb = x - d0 + kDpad - (DPL - 1);  // keyR index of d0 + DPL - 1
 #pragma unroll
-        for (int j = 0; j < DPL; ++j) {
-            const uint32_t key = (S[j] << 8) | (uint32_t)(d0 + j);
-            kmin = min(kmin, key);
-            atomicMin(&keyR[kb + (DPL - 1 - j)], key);
+        for (int j = 0; j < DPL; ++j) kmin = min(kmin, (S[j] << 8) | (uint32_t)(d0 + j));
+        if (right) {
+#pragma unroll
+            for (int j = 0; j < DPL; ++j) atomicMin(&keyR[kb + (DPL - 1 - j)], (S[j] << 8) | (uint32_t)(d0 + j));
         }
         kmin = row_min(kmin);
         const int dstar = (int)(kmin & 0xFF);
@@ -380,11 +381,11 @@ __device__ __forceinline__ void select_row(const SelectArgs &a, int y, uint32_t 
         const int d = dint_row[x];
         const int xr = x - d;
         bool lr_ok = true;
-        if (lr >= 0) lr_ok = xr >= 0 && abs(d - (int)(keyR[xr + kDpad] & 0xFF)) <= lr;
+        if (right && lr >= 0) lr_ok = xr >= 0 && abs(d - (int)(keyR[xr + kDpad] & 0xFF)) <= lr;
         const bool nz = d > 0, uq = uniq_row[x] != 0;
         a.flags[row + x] = (uint8_t)(uq | (lr_ok << 1) | (nz << 2));
         a.masked[row + x] = (uq && lr_ok && nz) ? dsub_row[x] : 0.0f;
-        a.disp_right[row + x] = (uint8_t)(keyR[x + kDpad] & 0xFF);
+        if (right) a.disp_right[row + x] = (uint8_t)(keyR[x + kDpad] & 0xFF);
         a.disp_int[row + x] = (uint8_t)d;
         a.cost_best[row + x] = s1_row[x];
         a.cost_second[row + x] = s2_row[x];
@@ -396,7 +397,7 @@ template <int DPL, int NDIR, bool SMALL, bool V16>
 __global__ __launch_bounds__(kSelBlock, sel_waves_per_simd(DPL, V16, SMALL)) void select_kernel(SelectArgs a)
 {
     extern __shared__ uint32_t smem[];
-    select_row<DPL, NDIR, SMALL, V16>(a, (int)blockIdx.x, smem);
+    select_row<DPL, NDIR, SMALL, V16>(a, (int)blockIdx.x, smem, !a.no_right);
 }
 
 // batch form: one block per (pair slot, row) item
@@ -405,7 +406,8 @@ __global__ __launch_bounds__(kSelBlock, sel_waves_per_simd(DPL, false, SMALL)) v
 {
     extern __shared__ uint32_t smem[];
     const uint32_t it = b.items[blockIdx.x];
-    select_row<DPL, NDIR, SMALL>(b.slots[it >> 20], (int)(it & 0xFFFFFu), smem);
+    const SelectArgs &a = b.slots[it >> 20];
+    select_row<DPL, NDIR, SMALL>(a, (int)(it & 0xFFFFFu), smem, !(b.no_right || a.no_right));
 }
 
 namespace {
