@@ -169,6 +169,7 @@ def learned_and_batch_legs(nat, args, out, inputs):
     g8 = min(64, npairs)
     b8 = nat.Batch([params8] * g8)
     outs8 = [b8.outputs() for _ in range(0, npairs, g8)]
+    tune8, _ = b8.autotune(Ls[:g8], Rs[:g8], outs8[0], reps=2)  # launch shape, as for the learned form
     for i in range(0, npairs, g8):
         b8.compute(Ls[i:i + g8], Rs[i:i + g8], outs8[i // g8])
     torch.cuda.synchronize()
@@ -207,7 +208,7 @@ def learned_and_batch_legs(nat, args, out, inputs):
     res["batch_256_sensor"] = {
         "pairs": npairs, "plain_8path_pairs_s": round(pairs8, 2), "learned_2path_net_pairs_s": round(pairs2, 2),
         "speedup": round(pairs2 / pairs8, 3), "plain_graph_launches": (npairs + g8 - 1) // g8,
-        "learned_graph_launches": 1, "net_trained": trained, "learned_tuning": tune2,
+        "learned_graph_launches": 1, "net_trained": trained, "plain_tuning": tune8, "learned_tuning": tune2,
         "quality_vs_8path": qm, "fallback": {"tau": tau, "threshold_frac": args.fallback_frac,
                                              "rate": round(float(fall.mean()), 4),
                                              "quality_after_fallback": qm_after},

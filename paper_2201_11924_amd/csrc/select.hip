@@ -2,7 +2,7 @@
 // uniqueness test, quadratic sub-pixel fit, left-right consistency check,
 // 3x3 median filter and depth = f*B/d.
 //
-// The selection pass owns one image row per 256-thread block.  Sixteen lanes
+// The selection pass owns one image row per 512-thread block.  Sixteen lanes
 // (one DPP row) hold one pixel's aggregated costs S(d) = sum_r L_r(p,d), dpl
 // disparities per lane, exactly as the aggregation pass laid them out.  The
 // right-image disparity needed by the LR check, dR(xr) = argmin_d S(xr+d, d),
@@ -215,40 +215,6 @@ __device__ __forceinline__ void store_row(uint16_t *dst, const uint32_t (&S)[DPL
     }
 }
 
-typedef unsigned short ushort2_t __attribute__((ext_vector_type(2)));
-
-// minimum of the lane's dpl 16-bit values of the row (packed 16-bit minima)
-template <int DPL>
-__device__ __forceinline__ uint32_t row_slice_min(const uint16_t *src)
-{
-    if constexpr (DPL == 1) {
-        return *src;
-    } else {
-        constexpr int NW = DPL / 2;
-        uint32_t w[NW];
-        if constexpr (NW % 4 == 0) {
-#pragma unroll
-            for (int i = 0; i < NW; i += 4) {
-                const uint4 v = *(const uint4 *)(src + 2 * i);
-                w[i] = v.x; w[i + 1] = v.y; w[i + 2] = v.z; w[i + 3] = v.w;
-            }
-        } else if constexpr (NW % 2 == 0) {
-#pragma unroll
-            for (int i = 0; i < NW; i += 2) {
-                const uint2 v = *(const uint2 *)(src + 2 * i);
-                w[i] = v.x; w[i + 1] = v.y;
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < NW; ++i) w[i] = *(const uint32_t *)(src + 2 * i);
-        }
-        ushort2_t m = __builtin_bit_cast(ushort2_t, w[0]);
-#pragma unroll
-        for (int i = 1; i < NW; ++i) m = __builtin_elementwise_min(m, __builtin_bit_cast(ushort2_t, w[i]));
-        return min((uint32_t)m.x, (uint32_t)m.y);
-    }
-}
-
 // Keeps the compiler from moving LDS accesses across this point; LDS
 // operations of one wavefront are performed in order, so lanes then see each
 // other's earlier writes without a block barrier.
@@ -332,19 +298,18 @@ __device__ __forceinline__ void select_row(const SelectArgs &a, int y, uint32_t 
         kmin = row_min(kmin);
         const int dstar = (int)(kmin & 0xFF);
         const uint32_t s1 = kmin >> 8;
-        // neighbours for the sub-pixel fit, then the winner's window d*-1 .. d*+1
-        // masked out of the row for the second-best search
+        // second best: the minimum of S outside the winner's window d*-1 .. d*+1,
+        // from the registers (d is in the window when d - d* + 1 is 0, 1 or 2;
+        // padding disparities hold 0xFFFF)
+        const int q = d0 + 1 - dstar;
+        uint32_t s2 = 0xFFFFu;
+#pragma unroll
+        for (int j = 0; j < DPL; ++j) s2 = min(s2, (uint32_t)(q + j) <= 2u ? 0xFFFFu : S[j]);
+        s2 = row_min(s2);
+        // neighbours for the sub-pixel fit, read back from the row in LDS
         wave_lds_order();
         uint32_t nb = 0;
-        if (lane == 0) {
-            if (dstar > 0 && dstar < D - 1) nb = ((uint32_t)my[dstar - 1] << 16) | my[dstar + 1];
-            if (dstar > 0) my[dstar - 1] = 0xFFFFu;
-            my[dstar] = 0xFFFFu;
-            if (dstar + 1 < kDpad) my[dstar + 1] = 0xFFFFu;
-        }
-        wave_lds_order();
-        uint32_t s2 = row_min(row_slice_min<DPL>(my + d0));
-        wave_lds_order();
+        if (lane == 0 && dstar > 0 && dstar < D - 1) nb = ((uint32_t)my[dstar - 1] << 16) | my[dstar + 1];
         if (lane == 0) {
             const int u = a.uniqueness_pct;
             const bool uniq = u == 0 || s2 == 0xFFFFu || 100u * s1 <= (uint32_t)(100 - u) * s2;
