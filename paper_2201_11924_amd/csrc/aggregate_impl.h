@@ -457,9 +457,15 @@ __device__ __forceinline__ T *uniform(T *p)
     return (T *)(((uint64_t)hi << 32) | lo);
 }
 
-template <int DPL, int LPL, bool WIDE, bool HORIZ, int TILE>
+// HDIR: 0 for lines that share an image row per clock (kinds 1 and 2); +1 / -1
+// for horizontal lines running left-to-right / right-to-left.  A horizontal
+// line's cR words slide by one column per clock, so the lane keeps its DPL words
+// in registers and reads one new word per clock (plus cL), at offsets that are
+// compile-time constants for a given direction.
+template <int DPL, int LPL, bool WIDE, int HDIR, int TILE>
 __device__ __forceinline__ void run_lines(const LineArgs &a, const BlockGeom &g, uint32_t (*tile)[TILE])
 {
+    constexpr bool HORIZ = HDIR != 0;
     using CW = CensusWord<WIDE>;
     using LO = LineOps<LPL>;
     using Word = typename CW::T;
@@ -577,6 +583,32 @@ __device__ __forceinline__ void run_lines(const LineArgs &a, const BlockGeom &g,
     else __builtin_amdgcn_s_waitcnt(vmcnt_encoding(0));
     __syncthreads();
 
+    // horizontal lines: the lane's sliding window of cR words, preloaded with the
+    // words of clock 0 that the first step keeps (tile indices within the line's
+    // slot: a column col of chunk 0 is at col - xm + kDpad - 1)
+    // (dx > 0: win[i] = cR(x0 - d0 - DPL + i) for i >= 1; dx < 0:
+    // win[i] = cR(x0 - d0 - DPL + 2 + i) for i <= DPL - 2; the other word is
+    // shifted out by the first step)
+    Word win[DPL];
+    if constexpr (HORIZ) {
+        constexpr int kFirst = HDIR > 0 ? 1 : 0;
+        const int idx0 = (HDIR > 0 ? kDpad - 1 - d0 - DPL : kDpad - d0 - DPL + 16) + kFirst;
+        if constexpr (DPL == 1) {
+            (void)idx0;
+        } else if constexpr (!WIDE) {
+            uint32_t w[DPL - 1], a0 = lds_addr((const Word *)&tile[0][0] + li * kSlot + idx0);
+            ds_read_run<DPL - 1>(a0, w);
+            lds_wait<DPL - 1>(a0, w);
+#pragma unroll
+            for (int i = 0; i < DPL - 1; ++i) win[kFirst + i] = w[i];
+        } else {
+            const Word *sl = (const Word *)&tile[0][0] + li * kSlot + idx0;
+#pragma unroll
+            for (int i = 0; i < DPL - 1; ++i) win[kFirst + i] = sl[i];
+        }
+        win[HDIR > 0 ? 0 : DPL - 1] = 0;
+    }
+
     for (int c = 0; c < nchunks; ++c) {
         const int buf = c % 3;
         const int c0 = c * kChunk;
@@ -617,7 +649,26 @@ __device__ __forceinline__ void run_lines(const LineArgs &a, const BlockGeom &g,
             const uint32_t tb = lds_addr(&tile[buf][0]);
             aL = tb + (uint32_t)(kDpad + kChunk - 1 + xlane) * 4;
             aR = tb + (uint32_t)(xlane + kDpad - d0 - DPL) * 4;
+        } else if constexpr (HORIZ && !WIDE) {
+            // the line's slot; clock K reads cL at window column xo(K) and the one
+            // new cR word (dx > 0: column x - d0; dx < 0: x - d0 - DPL + 1)
+            const uint32_t tb = lds_addr(&tile[buf][0]) + (uint32_t)(li * kSlot) * 4;
+            aL = tb + (uint32_t)(kDpad + kChunk - 1) * 4;
+            aR = tb + (uint32_t)(HDIR > 0 ? kDpad - 1 - d0 : kDpad - d0 - DPL) * 4;
         }
+        // horizontal lines: cL and the new cR word of clock K
+        auto fetch_slide = [&](auto kc, Word &wl, Word(&wn)[1]) {
+            constexpr int K = decltype(kc)::value;
+            constexpr int XO = HDIR > 0 ? K : kChunk - 1 - K;  // window column of clock K
+            if constexpr (!WIDE) {
+                wl = ds_read_at<XO * 4>(aL);
+                wn[0] = ds_read_at<XO * 4>(aR);
+            } else {
+                const Word *sl = (const Word *)&tile[buf][0] + li * kSlot;
+                wl = sl[kDpad + kChunk - 1 + XO];
+                wn[0] = sl[(HDIR > 0 ? kDpad - 1 - d0 : kDpad - d0 - DPL) + XO];
+            }
+        };
         auto fetch_clock = [&](auto kc, Word &wl, Word(&wr)[DPL]) {
             constexpr int K = decltype(kc)::value;
             if constexpr (!HORIZ && !WIDE) {
@@ -629,21 +680,41 @@ __device__ __forceinline__ void run_lines(const LineArgs &a, const BlockGeom &g,
                 fetch(buf, slot, x - xm, wl, wr);
             }
         };
-        Word wl_n, wr_n[DPL];
-        fetch_clock(std::integral_constant<int, 0>{}, wl_n, wr_n);
+        Word wl_n, wr_n[DPL], wn_n[1];
+        if constexpr (HORIZ) fetch_slide(std::integral_constant<int, 0>{}, wl_n, wn_n);
+        else fetch_clock(std::integral_constant<int, 0>{}, wl_n, wr_n);
         static_for<kChunk>([&](auto kc) {
             constexpr int k = decltype(kc)::value;
             const int t = c0 + k;
             const int s = t - skew;
             int x, row, xm, slot;
             locate(c0, k, x, row, xm, slot);
-            ready(wl_n, wr_n);
-            const Word wl = wl_n;
+            Word wl;
             Word wr[DPL];
+            if constexpr (HORIZ) {
+                if constexpr (!WIDE) lds_wait<1>(wl_n, wn_n);
+                wl = wl_n;
+                // slide the window one column and take in the new word
+                if constexpr (HDIR > 0) {
 #pragma unroll
-            for (int j = 0; j < DPL; ++j) wr[j] = wr_n[j];
-            // next clock's census words are read while this clock computes
-            if constexpr (k + 1 < kChunk) fetch_clock(std::integral_constant<int, k + 1>{}, wl_n, wr_n);
+                    for (int j = 0; j < DPL - 1; ++j) win[j] = win[j + 1];
+                    win[DPL - 1] = wn_n[0];
+                } else {
+#pragma unroll
+                    for (int j = DPL - 1; j > 0; --j) win[j] = win[j - 1];
+                    win[0] = wn_n[0];
+                }
+#pragma unroll
+                for (int j = 0; j < DPL; ++j) wr[j] = win[j];
+                if constexpr (k + 1 < kChunk) fetch_slide(std::integral_constant<int, k + 1>{}, wl_n, wn_n);
+            } else {
+                ready(wl_n, wr_n);
+                wl = wl_n;
+#pragma unroll
+                for (int j = 0; j < DPL; ++j) wr[j] = wr_n[j];
+                // next clock's census words are read while this clock computes
+                if constexpr (k + 1 < kChunk) fetch_clock(std::integral_constant<int, k + 1>{}, wl_n, wr_n);
+            }
             // (horizontal lines all span the image width: a per-lane constant and a
             // uniform test, so the check stays on the scalar unit)
             const bool active = HORIZ ? (len > 0 && t < W) : (uint32_t)s < (uint32_t)len;
@@ -746,9 +817,10 @@ __device__ __forceinline__ void aggregate_block(const AggregateArgs &a, int blk,
                                        la.W, la.H, kBlock / HL);
     if (g.kind == 0) {
         // horizontal lines: more lanes per line to shorten each step
-        run_lines<kDpad / HL, HL, WIDE, true, agg_tile_dwords<DPL, WIDE>()>(la, g, tile);
+        if (g.dx > 0) run_lines<kDpad / HL, HL, WIDE, 1, agg_tile_dwords<DPL, WIDE>()>(la, g, tile);
+        else run_lines<kDpad / HL, HL, WIDE, -1, agg_tile_dwords<DPL, WIDE>()>(la, g, tile);
     } else {
-        run_lines<DPL, kLanesPerLine, WIDE, false, agg_tile_dwords<DPL, WIDE>()>(la, g, tile);
+        run_lines<DPL, kLanesPerLine, WIDE, 0, agg_tile_dwords<DPL, WIDE>()>(la, g, tile);
     }
     __builtin_amdgcn_s_setprio(0);
 }
