@@ -82,12 +82,78 @@ __device__ __forceinline__ void census_tile(const uint8_t *__restrict__ img, int
     out[(size_t)y * W + x] = word;
 }
 
+// The same transform for a window size fixed at compile time (center-symmetric
+// mode): the comparisons unroll with constant LDS offsets, and the word is built
+// from the last comparison down, w = (w << 1) | [a > b], where [a > b] is the
+// sign bit of b - a and the shift-and-insert is one v_alignbit.
+template <int CW, int CH>
+__device__ __forceinline__ void cs_offsets(int k, int &oy, int &ox)
+{
+    constexpr int rw = CW / 2, rh = CH / 2;
+    if (k < rh * CW) {
+        oy = -rh + k / CW;
+        ox = -rw + k % CW;
+    } else {
+        oy = 0;
+        ox = -rw + (k - rh * CW);
+    }
+}
+
+template <typename Word, int CW, int CH>
+__device__ __forceinline__ void census_tile_cs(const uint8_t *__restrict__ img, int pitch, int W, int H,
+                                               Word *__restrict__ out, int bx, int by, uint8_t *tile)
+{
+    constexpr int rw = CW / 2, rh = CH / 2;
+    constexpr int tw = kCensusTx + CW - 1, th = kCensusTy + CH - 1;
+    constexpr int kBits = (CW * CH - 1) / 2;
+    static_assert(kBits <= 8 * (int)sizeof(Word), "word too narrow");
+    const int x0 = bx * kCensusTx - rw, y0 = by * kCensusTy - rh;
+    const int tid = threadIdx.y * kCensusTx + threadIdx.x;
+    for (int i = tid; i < tw * th; i += kCensusTx * kCensusTy) {
+        const int ty = i / tw, tx = i - ty * tw;
+        const int gx = min(max(x0 + tx, 0), W - 1), gy = min(max(y0 + ty, 0), H - 1);
+        tile[i] = img[(size_t)gy * pitch + gx];
+    }
+    __syncthreads();
+    const int x = bx * kCensusTx + threadIdx.x, y = by * kCensusTy + threadIdx.y;
+    if (x >= W || y >= H) return;
+    const uint8_t *ctr = &tile[(threadIdx.y + rh) * tw + threadIdx.x + rw];
+    uint32_t lo = 0, hi = 0;
+#pragma unroll
+    for (int k = kBits - 1; k >= 0; --k) {
+        int oy, ox;
+        cs_offsets<CW, CH>(k, oy, ox);
+        const uint32_t d = (uint32_t)ctr[-oy * tw - ox] - (uint32_t)ctr[oy * tw + ox];  // sign = [a > b]
+        if (kBits > 32) hi = __builtin_amdgcn_alignbit(hi, lo, 31);
+        lo = __builtin_amdgcn_alignbit(lo, d, 31);
+    }
+    if constexpr (sizeof(Word) == 8) out[(size_t)y * W + x] = ((uint64_t)hi << 32) | lo;
+    else out[(size_t)y * W + x] = lo;
+}
+
+// the window sizes with a compiled center-symmetric form; others (and the full
+// census) take the general loop
+template <typename Word>
+__device__ __forceinline__ void census_any(const uint8_t *img, int pitch, int W, int H, int cw, int ch, int mode,
+                                           Word *out, int bx, int by, uint8_t *tile)
+{
+    if (mode == 0) {
+        if (cw == 7 && ch == 9) return census_tile_cs<Word, 7, 9>(img, pitch, W, H, out, bx, by, tile);
+        if (cw == 9 && ch == 7) return census_tile_cs<Word, 9, 7>(img, pitch, W, H, out, bx, by, tile);
+        if (cw == 5 && ch == 5) return census_tile_cs<Word, 5, 5>(img, pitch, W, H, out, bx, by, tile);
+        if (cw == 7 && ch == 7) return census_tile_cs<Word, 7, 7>(img, pitch, W, H, out, bx, by, tile);
+        if constexpr (sizeof(Word) == 8)
+            if (cw == 9 && ch == 9) return census_tile_cs<Word, 9, 9>(img, pitch, W, H, out, bx, by, tile);
+    }
+    census_tile<Word>(img, pitch, W, H, cw, ch, mode, out, bx, by, tile);
+}
+
 template <typename Word>
 __global__ __launch_bounds__(256) void census_kernel(const uint8_t *__restrict__ img, int pitch, int W, int H, int cw,
                                                      int ch, int mode, Word *__restrict__ out)
 {
     extern __shared__ uint8_t tile[];
-    census_tile<Word>(img, pitch, W, H, cw, ch, mode, out, blockIdx.x, blockIdx.y, tile);
+    census_any<Word>(img, pitch, W, H, cw, ch, mode, out, blockIdx.x, blockIdx.y, tile);
 }
 
 // batch form: one block per (job, 32x8 tile) item; tile = by * ceil(W/32) + bx
@@ -98,7 +164,7 @@ __global__ __launch_bounds__(256) void census_batch_kernel(CensusBatch b)
     const uint32_t it = b.items[blockIdx.x];
     const CensusJob &j = b.jobs[it >> 20];
     const int t = (int)(it & 0xFFFFFu), tx = (j.W + kCensusTx - 1) / kCensusTx;
-    census_tile<Word>(j.img, j.pitch, j.W, j.H, j.cw, j.ch, j.mode, (Word *)j.out, t % tx, t / tx, tile);
+    census_any<Word>(j.img, j.pitch, j.W, j.H, j.cw, j.ch, j.mode, (Word *)j.out, t % tx, t / tx, tile);
 }
 
 hipError_t launch_census_batch(const CensusBatch &b, bool out64, hipStream_t s)
