@@ -258,8 +258,9 @@ int enqueue_batch(simsense_batch *b, hipStream_t s)
     return rc != SIMSENSE_OK ? rc : enqueue_post_batch(b, s);
 }
 
-// the learned pass sequence: matching, then per chunk of slots the features,
-// the net and the combination (with the per-slot uncertainty count), then post
+// the learned pass sequence: matching, then the fused net (which builds its
+// input features from the selection outputs) and the combination with the
+// per-slot uncertainty count, one launch over all slots, then post
 int enqueue_learned_batch(simsense_batch *b, simsense_net *net, float tau, unsigned *uncertain, hipStream_t s)
 {
     hipLaunchKernelGGL(zero_words, dim3(1), dim3(256), 0, s, uncertain, b->n);
@@ -270,23 +271,9 @@ int enqueue_learned_batch(simsense_batch *b, simsense_net *net, float tau, unsig
     const Slot &s0 = b->slots[0];
     const int W = s0.p.width, H = s0.p.height;
     const int64_t P = (int64_t)W * H;
-    const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(b->n, net->max_pixels / P));
+    const int chunk = b->n;  // the features are never stored: no buffer bounds the chunk
     for (int c0 = 0; c0 < b->n; c0 += chunk) {
         const int cn = std::min(chunk, b->n - c0);
-        for (int k = 0; k < cn; ++k) {
-            const Slot &sl = b->slots[c0 + k];
-            net::FeatureArgs fa{};
-            fa.job = b->d_cjobs + 2 * (c0 + k);  // the left image of the slot, as refreshed per call
-            fa.W = W;
-            fa.s1 = (const uint16_t *)(b->scratch + sl.off_s1);
-            fa.s2 = (const uint16_t *)(b->scratch + sl.off_s2);
-            fa.dint = b->scratch + sl.off_dint;
-            fa.max_disp = sl.p.max_disp;
-            fa.smax = (float)(sl.ndirs * (sl.bits + sl.p.p2));
-            fa.features = net->feat + (size_t)k * P * 8;
-            fa.P = P;
-            B_TRY(net::launch_features(fa, s));
-        }
         // the fused net + combination, one launch for the chunk when its slots'
         // buffers lie at equal distances (equal-sized slots do), else per slot
         auto gap = [&](size_t Slot::*off, int k) {
@@ -297,10 +284,22 @@ int enqueue_learned_batch(simsense_batch *b, simsense_net *net, float tau, unsig
             uniform = gap(&Slot::off_dsub, k) == gap(&Slot::off_dsub, 1) &&
                       gap(&Slot::off_masked, k) == gap(&Slot::off_masked, 1) &&
                       gap(&Slot::off_flags, k) == gap(&Slot::off_flags, 1);
+        // the net reads S1, S2 and d* of image i at one byte distance per image
+        for (int k = 1; k < cn && uniform; ++k)
+            uniform = gap(&Slot::off_s1, k) == gap(&Slot::off_s1, 1) && gap(&Slot::off_s2, k) == gap(&Slot::off_s1, 1) &&
+                      gap(&Slot::off_dint, k) == gap(&Slot::off_s1, 1);
         const int per = uniform ? cn : 1;
         for (int k = 0; k < cn; k += per) {
             const Slot &sl = b->slots[c0 + k];
-            net::InferArgs ia = net::infer_args(net, net->feat + (size_t)k * P * 8, per, H, W);
+            // the features are built inside the net from the selection outputs
+            net::InferArgs ia = net::infer_args(net, nullptr, per, H, W);
+            ia.ir_jobs = b->d_cjobs + 2 * (c0 + k);  // the left images, as refreshed per call
+            ia.s1 = (const uint16_t *)(b->scratch + sl.off_s1);
+            ia.s2 = (const uint16_t *)(b->scratch + sl.off_s2);
+            ia.dint = b->scratch + sl.off_dint;
+            ia.sel_stride = per > 1 ? gap(&Slot::off_s1, 1) : 0;
+            ia.max_disp = sl.p.max_disp;
+            ia.smax = (float)(sl.ndirs * (sl.bits + sl.p.p2));
             ia.d2_sub = (const float *)(b->scratch + sl.off_dsub);
             ia.masked = (float *)(b->scratch + sl.off_masked);
             ia.flags = b->scratch + sl.off_flags;

@@ -378,13 +378,20 @@ int simsense_learned_compute(simsense_handle *h, simsense_net *n, const uint8_t 
     if (rc != SIMSENSE_OK) return rc;
     rc = enqueue_match(h, left, right, pitch, s, nullptr, /*need_right=*/false);
     if (rc != SIMSENSE_OK) return rc;
-    FeatureArgs fa{};
-    fa.ir = left; fa.pitch = pitch; fa.W = p.width;
-    fa.s1 = h->cost_best; fa.s2 = h->cost_second; fa.dint = h->disp_int;
-    fa.max_disp = p.max_disp; fa.smax = (float)(h->ndirs * (h->bits + p.p2));
-    fa.features = n->feat; fa.P = P;
-    NET_TRY(launch_features(fa, s));
-    InferArgs ia = infer_args(n, n->feat, 1, p.height, p.width);
+    const float smax = (float)(h->ndirs * (h->bits + p.p2));
+    if (o->features) {
+        // the features themselves only when asked for: the net builds its own
+        FeatureArgs fa{};
+        fa.ir = left; fa.pitch = pitch; fa.W = p.width;
+        fa.s1 = h->cost_best; fa.s2 = h->cost_second; fa.dint = h->disp_int;
+        fa.max_disp = p.max_disp; fa.smax = smax;
+        fa.features = o->features; fa.P = P;
+        NET_TRY(launch_features(fa, s));
+    }
+    InferArgs ia = infer_args(n, nullptr, 1, p.height, p.width);
+    ia.ir = left; ia.ir_pitch = pitch;
+    ia.s1 = h->cost_best; ia.s2 = h->cost_second; ia.dint = h->disp_int;
+    ia.max_disp = p.max_disp; ia.smax = smax;
     ia.d2_sub = h->disp_sub; ia.masked = h->masked; ia.flags = h->flags_pre;
     NET_TRY(launch_infer(ia, s));
     rc = enqueue_post(h, h->masked, h->flags_pre, o, s);
@@ -392,7 +399,6 @@ int simsense_learned_compute(simsense_handle *h, simsense_net *n, const uint8_t 
     profile_end_call(h);
     if (o->disp_sub) NET_TRY(hipMemcpyAsync(o->disp_sub, h->disp_sub, P * 4, hipMemcpyDeviceToDevice, s));
     if (o->disp_int) NET_TRY(hipMemcpyAsync(o->disp_int, h->disp_int, P, hipMemcpyDeviceToDevice, s));
-    if (o->features) NET_TRY(hipMemcpyAsync(o->features, n->feat, P * 16, hipMemcpyDeviceToDevice, s));
     return SIMSENSE_OK;
 }
 

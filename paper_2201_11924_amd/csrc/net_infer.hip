@@ -162,6 +162,21 @@ __device__ __forceinline__ void zero_row(Smem &sm, int layer, int j)
 
 }  // namespace
 
+// The network's input channels of one pixel from the 2-path selection outputs,
+// evaluated as the features pass does (same float operations, same bf16
+// rounding), so both input routes give the same features bit for bit.
+struct RawFeat {
+    uint32_t ir, s1, s2, d;
+};
+
+__device__ __forceinline__ uint4 feature_of(const RawFeat &v, float smax, int max_disp)
+{
+    const float s2 = v.s2 == 0xFFFFu ? smax : fminf((float)v.s2, smax);
+    const float f0 = (float)v.ir / 255.0f, f1 = (float)v.s1 / smax, f2 = s2 / smax, f3 = (float)v.d / (float)max_disp;
+    return make_uint4(pack_bf16(f0, f1), pack_bf16(f2, f3), 0u, 0u);
+}
+
+template <bool FROM_SEL>
 __global__ __launch_bounds__(256, 2) void net_infer_kernel(InferArgs a)
 {
     __shared__ Smem sm;
@@ -177,6 +192,17 @@ __global__ __launch_bounds__(256, 2) void net_infer_kernel(InferArgs a)
     const int y0 = seg * a.seg_rows, y1 = min(H, y0 + a.seg_rows);
     const int64_t P = (int64_t)H * W;
     const uint4 *feat = (const uint4 *)a.feat + (int64_t)img * P;
+    const uint8_t *irp = a.ir;
+    int irpitch = a.ir_pitch;
+    if (FROM_SEL && a.ir_jobs) {
+        const CensusJob *j = (const CensusJob *)a.ir_jobs + 2 * img;
+        irp = j->img;
+        irpitch = j->pitch;
+    }
+    const int64_t soff = (int64_t)img * a.sel_stride;
+    const uint16_t *s1i = (const uint16_t *)((const uint8_t *)a.s1 + soff);
+    const uint16_t *s2i = (const uint16_t *)((const uint8_t *)a.s2 + soff);
+    const uint8_t *di = a.dint + soff;
 
     // weights as A fragments: lane holds co = 16 mb + col, k = 32 c + 8 quad .. +7
     bf16x8 w2[2][9], w3[2][9];
@@ -216,8 +242,23 @@ __global__ __launch_bounds__(256, 2) void net_infer_kernel(InferArgs a)
     const int fq = threadIdx.x & 127, fx = min(max(xb + fq, 0), W - 1);
     const bool fq_inside = fq < kRingW && xb + fq >= 0 && xb + fq < W;
     auto fetch = [&](int r) { return feat[(int64_t)min(max(r, 0), H - 1) * W + fx]; };
+    // (from the selection outputs: the raw values are loaded here and turned into
+    // features when they are stored, a step later, so no load is waited on early)
+    auto fetch_raw = [&](int r) {
+        const int64_t row = min(max(r, 0), H - 1), p = row * W + fx;
+        RawFeat v;
+        v.ir = irp[row * irpitch + fx];
+        v.s1 = s1i[p];
+        v.s2 = s2i[p];
+        v.d = di[p];
+        return v;
+    };
     uint4 next = make_uint4(0, 0, 0, 0);
-    if (threadIdx.x < 128) next = fetch(y0 - 4);
+    RawFeat next_raw{0u, 0u, 0u, 0u};
+    if (threadIdx.x < 128) {
+        if constexpr (FROM_SEL) next_raw = fetch_raw(y0 - 4);
+        else next = fetch(y0 - 4);
+    }
     unsigned unsure = 0;
     // layer-4 results of the previous step: row prow (-1: none), tiles wave and wave + 4
     float pres[2] = {0.0f, 0.0f}, pz[2] = {0.0f, 0.0f}, pd2[2] = {0.0f, 0.0f};
@@ -255,9 +296,13 @@ __global__ __launch_bounds__(256, 2) void net_infer_kernel(InferArgs a)
         __syncthreads();  // the previous step's readers of the feature slot are done
         if (threadIdx.x < kRingW) {
             const bool ok = fq_inside && r >= 0 && r < H;
+            if constexpr (FROM_SEL) next = feature_of(next_raw, a.smax, a.max_disp);
             sm.feat[slot_of(r)][threadIdx.x + 1] = ok ? next : make_uint4(0, 0, 0, 0);
         }
-        if (threadIdx.x < 128) next = fetch(r + 1);
+        if (threadIdx.x < 128) {
+            if constexpr (FROM_SEL) next_raw = fetch_raw(r + 1);
+            else next = fetch(r + 1);
+        }
         float d2v[2] = {0.0f, 0.0f};
         if (d2img) {
             const int64_t row = (int64_t)min(max(j4, 0), H - 1) * W;
@@ -349,7 +394,8 @@ hipError_t launch_infer(InferArgs a, hipStream_t s)
     const int64_t blocks = (int64_t)a.batch * a.segs * a.strips;
     if (blocks <= 0) return hipSuccess;
     if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(net_infer_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    if (a.feat) hipLaunchKernelGGL(net_infer_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(net_infer_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -97,7 +97,19 @@ struct CombineArgs {
 // disparity) on `batch` images whose per-pixel outputs lie `*_stride` elements
 // apart; masked / flags / d2_sub / out / uncertain may each be null.
 struct InferArgs {
-    const uint16_t *feat;  // bf16 [batch][H][W][8]
+    const uint16_t *feat;  // bf16 [batch][H][W][8], or null: built from the selection outputs below
+    // the feature inputs when feat is null (the learned form): left image (from
+    // `ir`/`ir_pitch`, or when ir_jobs is set from census jobs 2 i of image i),
+    // S1, S2, d* (image i's at i * sel_stride bytes past image 0's), and the
+    // scales of the features
+    const uint8_t *ir;
+    int ir_pitch;
+    const void *ir_jobs;
+    const uint16_t *s1, *s2;
+    const uint8_t *dint;
+    int64_t sel_stride;
+    int max_disp;
+    float smax;
     const uint16_t *w[4];  // forward layouts, bf16 [COUTP][kpad(CINP)]
     const float *b[4];     // fp32 [COUTP]
     const float *d2_sub;
