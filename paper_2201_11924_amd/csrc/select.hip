@@ -190,45 +190,30 @@ __device__ __forceinline__ void sum_paths(const Words<DPL> (&v)[NDIR], uint32_t 
 
 }  // namespace
 
-// A group's row of S(d) in LDS, as 16-bit values in disparity order: stores of
-// the lane's dpl values (pairs packed into words) and the matching loads.
-template <int DPL>
-__device__ __forceinline__ void store_row(uint16_t *dst, const uint32_t (&S)[DPL])
+// bitwise AND over the 16 lanes of a DPP row, in every lane of the row
+__device__ __forceinline__ uint32_t row_and(uint32_t v)
 {
-    if constexpr (DPL == 1) {
-        *dst = (uint16_t)S[0];
-    } else {
-        constexpr int NW = DPL / 2;
-        uint32_t w[NW];
-#pragma unroll
-        for (int i = 0; i < NW; ++i) w[i] = S[2 * i] | (S[2 * i + 1] << 16);
-        if constexpr (NW % 4 == 0) {
-#pragma unroll
-            for (int i = 0; i < NW; i += 4) *(uint4 *)(dst + 2 * i) = make_uint4(w[i], w[i + 1], w[i + 2], w[i + 3]);
-        } else if constexpr (NW % 2 == 0) {
-#pragma unroll
-            for (int i = 0; i < NW; i += 2) *(uint2 *)(dst + 2 * i) = make_uint2(w[i], w[i + 1]);
-        } else {
-#pragma unroll
-            for (int i = 0; i < NW; ++i) *(uint32_t *)(dst + 2 * i) = w[i];
-        }
-    }
+    v &= dpp<kRowRor8>(v);
+    v &= dpp<kRowRor4>(v);
+    v &= dpp<kRowRor2>(v);
+    v &= dpp<kRowRor1>(v);
+    return v;
 }
 
-// Keeps the compiler from moving LDS accesses across this point; LDS
-// operations of one wavefront are performed in order, so lanes then see each
-// other's earlier writes without a block barrier.
-__device__ __forceinline__ void wave_lds_order()
+// S[t] when 0 <= t < DPL, else 0xFFFF
+template <int DPL>
+__device__ __forceinline__ uint32_t pick_value(const uint32_t (&S)[DPL], int t)
 {
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_wave_barrier();
-    asm volatile("" ::: "memory");
+    uint32_t v = 0xFFFFu;
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) v = t == j ? S[j] : v;
+    return v;
 }
 
 template <int DPL>
 constexpr size_t select_lds_bytes(int W)
 {
-    return (size_t)kSelGroups * kLanesPerLine * DPL * 2 + ((size_t)kLanesPerLine * DPL + W) * 4 + (size_t)W * 10;
+    return ((size_t)kLanesPerLine * DPL + W) * 4 + (size_t)W * 10;
 }
 
 template <int DPL, int NDIR, bool SMALL, bool V16 = false>
@@ -237,12 +222,11 @@ __device__ __forceinline__ void select_row(const SelectArgs &a, int y, uint32_t 
     constexpr int kValBytes = V16 ? 2 : 1;
     constexpr int kDpad = kLanesPerLine * DPL;
     const int W = a.W, D = a.D;
-    // LDS: per pixel group a row of S (16-bit); right-image keys indexed by
-    // xr + Dpad (xr >= -(Dpad-1)); the row's per-pixel results, written to HBM
-    // in coalesced row stores after the pixel loop (the loop itself issues no
-    // global store, so its look-ahead loads are waited on precisely)
-    uint16_t *srow = (uint16_t *)smem;
-    uint32_t *keyR = (uint32_t *)(srow + kSelGroups * kDpad);
+    // LDS: right-image keys indexed by xr + Dpad (xr >= -(Dpad-1)); the row's
+    // per-pixel results, written to HBM in coalesced row stores after the pixel
+    // loop (the loop itself issues no global store, so its look-ahead loads are
+    // waited on precisely)
+    uint32_t *keyR = smem;
     float *dsub_row = (float *)(keyR + kDpad + W);
     uint16_t *s1_row = (uint16_t *)(dsub_row + W);
     uint16_t *s2_row = s1_row + W;
@@ -255,7 +239,6 @@ __device__ __forceinline__ void select_row(const SelectArgs &a, int y, uint32_t 
 
     const int lane = threadIdx.x % kLanesPerLine, group = threadIdx.x / kLanesPerLine;
     const int d0 = lane * DPL;
-    uint16_t *my = srow + group * kDpad;
     // the pixel loop keeps a ring of kRing pixel steps of path values in
     // registers, loaded kRing - 1 steps ahead; the loop is unrolled over the
     // ring so no register still awaiting its load is ever copied (a copy would
@@ -283,7 +266,6 @@ __device__ __forceinline__ void select_row(const SelectArgs &a, int y, uint32_t 
 #pragma unroll
             for (int j = 0; j < DPL; ++j) S[j] = d0 + j < D ? S[j] : 0xFFFFu;
         }
-        store_row<DPL>(my + d0, S);
 
         // winner key (S << 8 | d): the minimum gives the lowest cost and, among
         // equal costs, the lowest d; the same key is scattered to xr = x - d
@@ -306,10 +288,10 @@ __device__ __forceinline__ void select_row(const SelectArgs &a, int y, uint32_t 
 #pragma unroll
         for (int j = 0; j < DPL; ++j) s2 = min(s2, (uint32_t)(q + j) <= 2u ? 0xFFFFu : S[j]);
         s2 = row_min(s2);
-        // neighbours for the sub-pixel fit, read back from the row in LDS
-        wave_lds_order();
-        uint32_t nb = 0;
-        if (lane == 0 && dstar > 0 && dstar < D - 1) nb = ((uint32_t)my[dstar - 1] << 16) | my[dstar + 1];
+        // neighbours for the sub-pixel fit, S(d*-1) and S(d*+1): the lane holding
+        // one picks it from its registers, every other lane contributes all ones,
+        // and an AND over the row gathers both halves into one word
+        const uint32_t nb = row_and((pick_value<DPL>(S, dstar - 1 - d0) << 16) | pick_value<DPL>(S, dstar + 1 - d0));
         if (lane == 0) {
             const int u = a.uniqueness_pct;
             const bool uniq = u == 0 || s2 == 0xFFFFu || 100u * s1 <= (uint32_t)(100 - u) * s2;
