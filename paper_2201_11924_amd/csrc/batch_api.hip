@@ -212,8 +212,9 @@ __global__ void zero_words(unsigned *c, int n)
 int enqueue_match_batch(simsense_batch *b, hipStream_t s, bool need_right = true)
 {
     const int ngroups = (int)b->agg_groups.size();
-    if (ngroups > 0) B_TRY(launch_zero_counters(b->d_counters, ngroups, s));
     CensusBatch cb{};
+    cb.zero = b->d_counters;  // the census launch clears the work-queue counters
+    cb.nzero = ngroups;
     cb.jobs = b->d_cjobs;
     cb.items = b->d_items + b->census_item_off;
     cb.nitems = b->census_nitems;

@@ -150,9 +150,11 @@ __device__ __forceinline__ void census_any(const uint8_t *img, int pitch, int W,
 
 template <typename Word>
 __global__ __launch_bounds__(256) void census_kernel(const uint8_t *__restrict__ img, int pitch, int W, int H, int cw,
-                                                     int ch, int mode, Word *__restrict__ out)
+                                                     int ch, int mode, Word *__restrict__ out, unsigned *zero, int nzero)
 {
     extern __shared__ uint8_t tile[];
+    const int tid = threadIdx.y * kCensusTx + threadIdx.x;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && tid < nzero) zero[tid] = 0u;
     census_any<Word>(img, pitch, W, H, cw, ch, mode, out, blockIdx.x, blockIdx.y, tile);
 }
 
@@ -161,6 +163,8 @@ template <typename Word>
 __global__ __launch_bounds__(256) void census_batch_kernel(CensusBatch b)
 {
     extern __shared__ uint8_t tile[];
+    const int tid = threadIdx.y * kCensusTx + threadIdx.x;
+    if (blockIdx.x == 0 && tid < b.nzero) b.zero[tid] = 0u;
     const uint32_t it = b.items[blockIdx.x];
     const CensusJob &j = b.jobs[it >> 20];
     const int t = (int)(it & 0xFFFFFu), tx = (j.W + kCensusTx - 1) / kCensusTx;
@@ -170,6 +174,7 @@ __global__ __launch_bounds__(256) void census_batch_kernel(CensusBatch b)
 hipError_t launch_census_batch(const CensusBatch &b, bool out64, hipStream_t s)
 {
     if (b.nitems == 0) return hipSuccess;
+    if (b.nzero < 0 || b.nzero > kCensusTx * kCensusTy) return hipErrorInvalidValue;
     const size_t lds = (size_t)(kCensusTx + b.max_cw - 1) * (kCensusTy + b.max_ch - 1);
     if (out64)
         hipLaunchKernelGGL(census_batch_kernel<uint64_t>, dim3(b.nitems), dim3(kCensusTx, kCensusTy), lds, s, b);
@@ -181,17 +186,18 @@ hipError_t launch_census_batch(const CensusBatch &b, bool out64, hipStream_t s)
 int census_tiles(int W, int H) { return ((W + kCensusTx - 1) / kCensusTx) * ((H + kCensusTy - 1) / kCensusTy); }
 
 hipError_t launch_census(const uint8_t *img, int pitch, int W, int H, int cw, int ch, int mode, void *out,
-                         bool out64, hipStream_t s)
+                         bool out64, hipStream_t s, unsigned *zero, int nzero)
 {
+    if (nzero < 0 || nzero > kCensusTx * kCensusTy || (nzero > 0 && !zero)) return hipErrorInvalidValue;
     dim3 grid((W + kCensusTx - 1) / kCensusTx, (H + kCensusTy - 1) / kCensusTy);
     dim3 block(kCensusTx, kCensusTy);
     size_t lds = (size_t)(kCensusTx + cw - 1) * (kCensusTy + ch - 1);
     if (out64)
         hipLaunchKernelGGL(census_kernel<uint64_t>, grid, block, lds, s, img, pitch, W, H, cw, ch, mode,
-                           (uint64_t *)out);
+                           (uint64_t *)out, zero, nzero);
     else
         hipLaunchKernelGGL(census_kernel<uint32_t>, grid, block, lds, s, img, pitch, W, H, cw, ch, mode,
-                           (uint32_t *)out);
+                           (uint32_t *)out, zero, nzero);
     return hipGetLastError();
 }
 

@@ -78,8 +78,10 @@ struct PostArgs {
 
 hipError_t launch_ir_noise(const uint8_t *in, const float *gamma, const float *n, uint8_t *out,
                            int64_t count, hipStream_t s);
+// (zero, nzero: counters the census launch clears on the way, so the work-queue
+// launch that follows needs no kernel of its own for that)
 hipError_t launch_census(const uint8_t *img, int pitch, int W, int H, int cw, int ch, int mode,
-                         void *out, bool out64, hipStream_t s);
+                         void *out, bool out64, hipStream_t s, unsigned *zero = nullptr, int nzero = 0);
 struct AggregateQueue {
     const AggregateArgs *slots;  // per pair slot (device)
     const uint32_t *items;       // slot << 20 | block, longest first (device)
@@ -136,6 +138,8 @@ struct CensusBatch {
     const CensusJob *jobs;
     const uint32_t *items;
     int nitems, max_cw, max_ch;
+    unsigned *zero;  // counters cleared by the first block (nzero of them)
+    int nzero;
 };
 struct SelectBatch {
     const SelectArgs *slots;
