@@ -163,6 +163,46 @@ def test_features_and_learned_path_match_oracle(nat, orc):
     net.close()
 
 
+def test_learned_path_features_built_in_the_net_equal_the_features_pass(nat, orc):
+    """The learned path's net builds its input features from the selection
+    outputs; the result must equal the net run on the features pass's output
+    (then the median), bit for bit, for one pair and for a batch."""
+    import torch
+    from synth import PairSpec, make_pair
+    W, H, D = 150, 70, 64
+    params2 = dict(width=W, height=H, max_disp=D, census_w=7, census_h=9, census_mode=0, p1=7, p2=86,
+                   uniqueness_pct=10, lr_max_diff=1, num_paths=2, median=3, subpixel=1, focal_px=400.0,
+                   baseline_m=0.055)
+    rng = np.random.default_rng(5)
+    params = [(w, rng.uniform(-0.05, 0.05, b.shape)) for w, b in no.init_params(4)]
+    net = nat.Net(3 * W * H, seed=0)
+    net.set_state(no.flatten(params))
+    ss = nat.SimSense(params2)
+    Ls, Rs, refs = [], [], []
+    for seed in (21, 22, 23):
+        pr = make_pair(PairSpec(W, H, planes=4, dmin=4, dmax=50, noise="gauss", sigma=3.0), seed)
+        L, R = dev(orc.ir_noise(pr.left, pr.gamma_l, pr.n_l)), dev(orc.ir_noise(pr.right, pr.gamma_r, pr.n_r))
+        out = nat.learned_compute(ss, net, L, R, extras=True)
+        f = out["features"].view(torch.int16).reshape(1, H, W, 8).contiguous()
+        m = net.infer(f, d2_sub=out["disp_sub"].reshape(1, H, W), raw=False)["masked"]
+        torch.cuda.synchronize()
+        ref = orc.median3(m[0].cpu().numpy().astype(np.float64)).astype(np.float32)
+        assert np.array_equal(out["disp"].cpu().numpy(), ref), seed
+        Ls.append(L)
+        Rs.append(R)
+        refs.append(out["disp"].cpu().numpy())
+    b = nat.Batch([params2] * 3)
+    outs = b.outputs()
+    unc = torch.zeros(3, dtype=torch.int32, device="cuda")
+    b.learned_compute(net, Ls, Rs, outs, 0.5, unc)
+    torch.cuda.synchronize()
+    for o, r in zip(outs, refs):
+        assert np.array_equal(o["disp"].cpu().numpy(), r)
+    b.close()
+    ss.close()
+    net.close()
+
+
 @pytest.mark.parametrize("B,H,W", [(2, 200, 250), (1, 5, 7), (3, 91, 81), (1, 1, 300), (1, 181, 1)])
 def test_fused_inference_equals_layered_forward(nat, B, H, W):
     """The fused kernel (row-strip LDS rings, several strips and row segments

@@ -91,7 +91,7 @@ def test_ir_noise_bit_exact(orc, nat):
 
 
 @pytest.mark.parametrize("cw,ch,mode", [(7, 9, 0), (9, 7, 0), (7, 9, 1), (5, 5, 1), (3, 3, 0), (11, 11, 0),
-                                        (1, 3, 0)])
+                                        (1, 3, 0), (5, 5, 0), (7, 7, 0), (9, 9, 0)])
 def test_census_bit_exact(orc, nat, cw, ch, mode):
     rng = np.random.default_rng(cw * 100 + ch + mode)
     for W, H in ((37, 29), (64, 8), (1, 5), (130, 67)):
