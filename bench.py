@@ -105,13 +105,13 @@ def generate_batch_inputs(args):
     """Host-side pair generation for the batch legs, in worker processes started
     before this process touches the GPU."""
     from synth import CONFIGS, pair_seed
-    from synth.stereo import c1_like
-    cfg = CONFIGS["c1"]
+    from synth.stereo import sensor_like
+    cfg = CONFIGS["pair_1280x720_d128"]
     sensor = _pool_generate([(cfg["spec"], pair_seed(4, i)) for i in range(args.batch_pairs)], args.workers)
     shapes = [(320, 240, 64), (640, 480, 96), (848, 480, 128), (1280, 720, 128)]
     specs, plist = [], []
     for si, (w, h, d) in enumerate(shapes):
-        c = c1_like(w, h, d)
+        c = sensor_like(w, h, d)
         for i in range(16):
             specs.append((c["spec"], pair_seed(2, 16 * si + i)))
             plist.append(c["params"])
@@ -124,8 +124,8 @@ def learned_and_batch_legs(nat, args, out, inputs):
     import torch
     from paper_2201_11924_amd.train import load_checkpoint, metrics
     from synth import CONFIGS, pair_seed
-    from synth.stereo import c1_like
-    cfg = CONFIGS["c1"]
+    from synth.stereo import sensor_like
+    cfg = CONFIGS["pair_1280x720_d128"]
     params8 = cfg["params"]
     params2 = dict(params8, num_paths=2)
     W, H, D = params8["width"], params8["height"], params8["max_disp"]
@@ -253,11 +253,11 @@ def paper_shape_leg(nat, reps=100):
     """Plain SGM at the shape the paper times: 960x540, 4 paths, D = 64/96/128/256."""
     import torch
     from synth import make_pair, pair_seed
-    from synth.stereo import c1_like
+    from synth.stereo import sensor_like
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     res, res_b = {}, {}
     for i, D in enumerate(sorted(PAPER_TABLE2_SGM_FPS)):
-        cfg = c1_like(960, 540, D)
+        cfg = sensor_like(960, 540, D)
         pr = make_pair(cfg["spec"], pair_seed(5, i))
         L = nat.ir_noise(t(pr.left), t(pr.gamma_l), t(pr.n_l))
         R = nat.ir_noise(t(pr.right), t(pr.gamma_r), t(pr.n_r))
@@ -325,7 +325,7 @@ def main():
     import paper_2201_11924_amd.native as nat
     from synth import CONFIGS, make_pair, pair_seed
 
-    cfg = CONFIGS["c1"]
+    cfg = CONFIGS["pair_1280x720_d128"]
     params = cfg["params"]
     W, H, D, P = params["width"], params["height"], params["max_disp"], params["num_paths"]
     pair = make_pair(cfg["spec"], pair_seed(1, 0))

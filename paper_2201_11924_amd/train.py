@@ -27,7 +27,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-from synth.stereo import c1_like, make_pair, pair_seed  # noqa: E402
+from synth.stereo import sensor_like, make_pair, pair_seed  # noqa: E402
 
 
 def _gen(args):
@@ -185,7 +185,7 @@ def main(argv=None):
     args = ap.parse_args(argv)
     log = lambda s: print(s, flush=True)
 
-    cfg = c1_like(args.width, args.height, args.max_disp)
+    cfg = sensor_like(args.width, args.height, args.max_disp)
     t0 = time.time()
     train_raw = generate([(cfg["spec"], pair_seed(3, i)) for i in range(args.pairs)], args.workers)
     eval_raw = generate([(cfg["spec"], pair_seed(3, 1_000 + i) + 500_000) for i in range(args.eval_pairs)],

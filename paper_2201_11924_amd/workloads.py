@@ -30,7 +30,7 @@ CHECKPOINT = os.path.join(ROOT, "paper_2201_11924_amd", "weights", "surrogate_64
 
 def _pair(nat, torch):
     from synth import CONFIGS, make_pair
-    cfg = CONFIGS["c1"]
+    cfg = CONFIGS["pair_1280x720_d128"]
     pr = make_pair(cfg["spec"], 1_000_000)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     L = nat.ir_noise(t(pr.left), t(pr.gamma_l), t(pr.n_l))

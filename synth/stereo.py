@@ -43,9 +43,9 @@ def _rng(seed: int, stream: int) -> np.random.Generator:
     return np.random.Generator(np.random.Philox(np.random.SeedSequence([int(seed), int(stream)])))
 
 
-def pair_seed(config_index: int, pair_index: int) -> int:
-    """Seed of pair ``pair_index`` of workload ``config_index``."""
-    return 1_000_000 * int(config_index) + int(pair_index)
+def pair_seed(workload_index: int, pair_index: int) -> int:
+    """Seed of pair ``pair_index`` of workload ``workload_index``."""
+    return 1_000_000 * int(workload_index) + int(pair_index)
 
 
 @dataclasses.dataclass(frozen=True)
@@ -171,17 +171,17 @@ _BASE = dict(census_w=7, census_h=9, census_mode=0, p1=7, p2=86, uniqueness_pct=
              lr_max_diff=1, num_paths=8, median=3, subpixel=1, baseline_m=0.055)
 
 CONFIGS: Dict[str, dict] = {
-    "c0": dict(spec=PairSpec(320, 240, planes=6, dmin=4, dmax=60, noise="gauss", sigma=3.0),
+    "pair_320x240_d64": dict(spec=PairSpec(320, 240, planes=6, dmin=4, dmax=60, noise="gauss", sigma=3.0),
                params=dict(_BASE, width=320, height=240, max_disp=64, focal_px=400.0),
-               index=0, pairs=1),
-    "c1": dict(spec=PairSpec(1280, 720, planes=12, dmin=8, dmax=120, noise="gauss", sigma=4.0,
+               pairs=1),
+    "pair_1280x720_d128": dict(spec=PairSpec(1280, 720, planes=12, dmin=8, dmax=120, noise="gauss", sigma=4.0,
                              gain_sd=0.05),
                params=dict(_BASE, width=1280, height=720, max_disp=128, focal_px=920.0),
-               index=1, pairs=1),
+               pairs=1),
 }
 
 
-def c1_like(width: int, height: int, max_disp: int) -> dict:
+def sensor_like(width: int, height: int, max_disp: int) -> dict:
     """A pair recipe and parameter set generated as for the 1280x720 sensor workload."""
     dmax = min(120.0, max_disp - 8.0)
     return dict(spec=PairSpec(width, height, planes=12, dmin=min(8.0, dmax), dmax=dmax,

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from synth import PairSpec, make_pair
-from synth.stereo import c1_like
+from synth.stereo import sensor_like
 
 pytestmark = pytest.mark.gpu
 
@@ -30,7 +30,7 @@ SHAPES = [(320, 240, 64), (97, 61, 37), (640, 480, 96), (160, 90, 128), (64, 48,
 def make_batch_inputs(orc, shapes, seed0=100):
     params, lefts, rights = [], [], []
     for i, (W, H, D) in enumerate(shapes):
-        cfg = c1_like(W, H, D)
+        cfg = sensor_like(W, H, D)
         p = dict(cfg["params"])
         if i % 3 == 1:
             p["num_paths"] = 4
@@ -108,7 +108,7 @@ def test_learned_batch_matches_single_pair_learned_path(orc, nat):
     import torch
     from oracle import net_oracle as no
     W, H, D = 200, 120, 64
-    cfg = c1_like(W, H, D)
+    cfg = sensor_like(W, H, D)
     p2 = dict(cfg["params"], num_paths=2)
     lefts, rights = [], []
     for i in range(5):

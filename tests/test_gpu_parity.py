@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from synth import CONFIGS, PairSpec, make_pair, make_shift_pair
-from synth.stereo import c1_like
+from synth.stereo import sensor_like
 
 pytestmark = pytest.mark.gpu
 
@@ -101,9 +101,9 @@ def test_census_bit_exact(orc, nat, cw, ch, mode):
 
 
 def test_small_workload_full_parity(orc, nat):
-    cfg = CONFIGS["c0"]
+    cfg = CONFIGS["pair_320x240_d64"]
     left, right = noisy_pair(orc, cfg["spec"], 0)
-    ref, g = compare(orc, nat, cfg["params"], left, right, volume=True, label="c0")
+    ref, g = compare(orc, nat, cfg["params"], left, right, volume=True, label="pair 320x240 D=64")
     assert (g["flags"] & 8).mean() > 0.5
 
 
@@ -129,9 +129,9 @@ def test_constant_shift_recovers_disparity(orc, nat):
 
 def test_sensor_size_parity_and_determinism(orc, nat):
     import torch
-    cfg = CONFIGS["c1"]
+    cfg = CONFIGS["pair_1280x720_d128"]
     left, right = noisy_pair(orc, cfg["spec"], 1_000_000)
-    compare(orc, nat, cfg["params"], left, right, label="c1")
+    compare(orc, nat, cfg["params"], left, right, label="pair 1280x720 D=128")
     ss = nat.SimSense(cfg["params"])
     a = ss(dev(left), dev(right))
     b = ss(dev(left), dev(right))
@@ -140,9 +140,9 @@ def test_sensor_size_parity_and_determinism(orc, nat):
         assert torch.equal(x, y)
 
 
-def test_c1_like_other_sizes(orc, nat):
+def test_sensor_like_other_sizes(orc, nat):
     for (W, H, D) in ((640, 480, 96), (848, 480, 128)):
-        cfg = c1_like(W, H, D)
+        cfg = sensor_like(W, H, D)
         left, right = noisy_pair(orc, cfg["spec"], W + D)
         compare(orc, nat, cfg["params"], left, right, label=f"{W}x{H}")
 

@@ -14,7 +14,7 @@ def test_reproducible_and_seed_dependent():
 
 
 def test_speckle_statistics():
-    spec = CONFIGS["c1"]["spec"]
+    spec = CONFIGS["pair_1280x720_d128"]["spec"]
     p = make_pair(spec, pair_seed(1, 0))
     dots = p.left >= 150
     assert abs(dots.mean() - 0.15) < 0.005
