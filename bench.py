@@ -374,6 +374,18 @@ def main():
                 "peak": round(VALU_PEAK_OPS / 1e12, 3), "unit": "Tops/s", "frac": round(achieved / VALU_PEAK_OPS, 4),
                 "traffic": measured_traffic(),
                 "ops_per_launch": agg_ops, "avg_launch_us": round(agg_s * 1e6, 2)}
+    # floors of the whole step: with 8 paths the summed costs cannot stay on
+    # chip, so at least one uint16 write and read of W*H*D values, plus the two
+    # images in and depth, disparity and flags out; and the aggregation's
+    # operations at the VALU peak
+    step_s = ms_step / 1000.0
+    hbm_floor_bytes = 4 * vol + (2 + 4 + 4 + 1) * W * H
+    floors = {"hbm_bytes": hbm_floor_bytes, "hbm_us": round(hbm_floor_bytes / HBM_PEAK * 1e6, 2),
+              "valu_ops": agg_ops, "valu_us": round(agg_ops / VALU_PEAK_OPS * 1e6, 2),
+              "step_us": round(step_s * 1e6, 2),
+              "hbm_frac": round(hbm_floor_bytes / HBM_PEAK / step_s, 4),
+              "valu_frac": round(agg_ops / VALU_PEAK_OPS / step_s, 4)}
+    floors["roofline_fraction"] = max(floors["hbm_frac"], floors["valu_frac"])
     out = {
         "metric": "stereo pairs/sec & Mpix·disp/s at 1280×720 D=128: 8-path SGM vs 2-path+net",
         "value": round(pairs_s, 2), "unit": "pairs/s",
@@ -387,6 +399,7 @@ def main():
         "pass_us": {k: round(v / calls * 1000.0, 2) for k, v in pass_ms.items()},
         "wall_s": round(wall, 3),
         "roofline": roofline,
+        "step_floors": floors,
     }
     ss.close()
     if not args.no_paper_shape:

@@ -43,7 +43,7 @@ static int validate(const simsense_params *p)
     if (p->census_w * p->census_h < 3) return SIMSENSE_ERR_INVALID_ARGUMENT;
     const int bits = census_bits(p->census_w, p->census_h, p->census_mode);
     if (bits > 64 || p->census_w > 65 || p->census_h > 65) return SIMSENSE_ERR_INVALID_ARGUMENT;
-    if (p->block_w < 1 || p->block_h < 1 || p->block_w > 31 || p->block_h > 31 || !(p->block_w & 1) ||
+    if (p->block_w < 1 || p->block_h < 1 || p->block_w > 2 * kMaxBlockHalf + 1 || p->block_h > 2 * kMaxBlockHalf + 1 || !(p->block_w & 1) ||
         !(p->block_h & 1))
         return SIMSENSE_ERR_INVALID_ARGUMENT;
     const bool block = p->block_w * p->block_h > 1;

@@ -96,6 +96,7 @@ hipError_t launch_select(const SelectArgs &a, hipStream_t s);
 hipError_t launch_post(const PostArgs &a, hipStream_t s);
 // Semi-global block matching: the block-cost volume and the aggregation fed
 // from it (16-bit path values, one block per line block).
+constexpr int kMaxBlockHalf = 15;  // SGBM blocks are at most 31 x 31
 struct BlockCostArgs {
     const void *census_l, *census_r;  // uint32 words, or uint64 when bits > 32
     int W, H, bits, bw, bh;

@@ -15,39 +15,116 @@ namespace ss {
 namespace {
 
 // ---------------------------------------------------------------- block costs
-// 16 pixels of one row per 256-thread block, one 16-lane row per pixel, dpl
-// disparities per lane.
+// 16 pixels of one row per 256-thread block, one 16-lane row per pixel, DPL
+// disparities per lane.  The window rows go through LDS one at a time (double
+// buffered, the next row fetched into registers while the current one is
+// summed): the left census words the 16 windows cover and the right words
+// they reach at every disparity, so every sample is an LDS read.
 template <int DPL, bool WIDE>
 __global__ __launch_bounds__(256) void block_cost_kernel(BlockCostArgs a)
 {
     using CW = CensusWord<WIDE>;
     using Word = typename CW::T;
-    const int lane = threadIdx.x & 15, px = threadIdx.x >> 4;
-    const int x = blockIdx.x * 16 + px, y = blockIdx.y;
-    if (x >= a.W) return;
-    const int W = a.W, H = a.H, d0 = lane * DPL;
+    constexpr int kDpad = kLanesPerLine * DPL;
+    constexpr int kLeftWords = 16 + 2 * kMaxBlockHalf;
+    constexpr int kRightWords = kLeftWords + kDpad - 1;
+    constexpr int kFetch = (kLeftWords + kRightWords + 255) / 256;
+    __shared__ Word sl[2][kLeftWords], sr[2][kRightWords];
+    const int tid = threadIdx.x, lane = tid & 15, px = tid >> 4;
+    const int W = a.W, H = a.H, y = blockIdx.y, x0 = blockIdx.x * 16, x = x0 + px;
+    const int hw = a.bw / 2, hh = a.bh / 2, d0 = lane * DPL;
+    // window columns (clamped to the image) and the right columns they reach;
+    // right word k holds column rlo + k (columns left of the image are never
+    // counted: their samples cost the full bit count)
+    const int xlo = max(x0 - hw, 0), xhi = min(x0 + 15 + hw, W - 1);
+    const int rlo = xlo - (kDpad - 1), nl = xhi - xlo + 1, n = nl + (xhi - rlo + 1);
     const Word *cl = (const Word *)a.census_l, *cr = (const Word *)a.census_r;
+    auto fetch = [&](int v, Word (&g)[kFetch]) {
+        const size_t row = (size_t)min(max(y + v, 0), H - 1) * W;
+#pragma unroll
+        for (int k = 0; k < kFetch; ++k) {
+            const int i = tid + 256 * k, col = i < nl ? xlo + i : rlo + (i - nl);
+            g[k] = i < n && col >= 0 ? (i < nl ? cl[row + col] : cr[row + col]) : Word(0);
+        }
+    };
+    auto put = [&](int buf, const Word (&g)[kFetch]) {
+#pragma unroll
+        for (int k = 0; k < kFetch; ++k) {
+            const int i = tid + 256 * k;
+            if (i < nl) sl[buf][i] = g[k];
+            else if (i < n) sr[buf][i - nl] = g[k];
+        }
+    };
     uint32_t acc[DPL];
 #pragma unroll
     for (int j = 0; j < DPL; ++j) acc[j] = 0;
-    for (int v = -(a.bh / 2); v <= a.bh / 2; ++v) {
-        const int cy = min(max(y + v, 0), H - 1);
-        const Word *rl = cl + (size_t)cy * W, *rr = cr + (size_t)cy * W;
-        for (int u = -(a.bw / 2); u <= a.bw / 2; ++u) {
-            const int cx = min(max(x + u, 0), W - 1);
-            const Word wl = rl[cx];
+    const int xc = min(x, W - 1);
+    const uint32_t bits = (uint32_t)a.bits;
+    const bool inner = rlo >= 0;  // no sample reaches left of the image
+    Word g[kFetch];
+    fetch(-hh, g);
+    put(0, g);
+    __syncthreads();
+    for (int v = -hh; v <= hh; ++v) {
+        const int buf = (v + hh) & 1;
+        if (v < hh) fetch(v + 1, g);
+        for (int u = -hw; u <= hw; ++u) {
+            const int cx = min(max(xc + u, 0), W - 1);
+            const Word wl = sl[buf][cx - xlo];
+            const Word *rr = &sr[buf][cx - d0 - rlo];
+            if (inner) {
 #pragma unroll
-            for (int j = 0; j < DPL; ++j) {
-                const int xs = cx - d0 - j;
-                const uint32_t c = CW::hamming(wl, rr[max(xs, 0)]);
-                acc[j] += xs >= 0 ? c : (uint32_t)a.bits;
+                for (int j = 0; j < DPL; ++j) acc[j] += CW::hamming(wl, rr[-j]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < DPL; ++j) acc[j] += cx - d0 - j >= 0 ? CW::hamming(wl, rr[-j]) : bits;
             }
         }
+        if (v < hh) put(buf ^ 1, g);
+        __syncthreads();
     }
-    store_u16<DPL>(a.vol + ((size_t)y * W + x) * (kLanesPerLine * DPL) + d0, acc);
+    if (x < W) store_u16<DPL>(a.vol + ((size_t)y * W + x) * kDpad + d0, acc);
 }
 
 // ---------------------------------------------------------------- aggregation
+// A lane's DPL 16-bit costs as loaded: packed two per word (one word for DPL 1)
+template <int DPL>
+constexpr int packed_words() { return DPL == 1 ? 1 : DPL / 2; }
+
+template <int DPL>
+__device__ __forceinline__ void load_packed(const uint16_t *src, uint32_t (&w)[packed_words<DPL>()])
+{
+    constexpr int NW = packed_words<DPL>();
+    if constexpr (DPL == 1) {
+        w[0] = *src;
+    } else {
+        const uint32_t *p = (const uint32_t *)src;
+        if constexpr (NW % 4 == 0) {
+#pragma unroll
+            for (int i = 0; i < NW; i += 4) {
+                const uint4 q = *(const uint4 *)(p + i);
+                w[i] = q.x; w[i + 1] = q.y; w[i + 2] = q.z; w[i + 3] = q.w;
+            }
+        } else if constexpr (NW % 2 == 0) {
+#pragma unroll
+            for (int i = 0; i < NW; i += 2) {
+                const uint2 q = *(const uint2 *)(p + i);
+                w[i] = q.x; w[i + 1] = q.y;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < NW; ++i) w[i] = p[i];
+        }
+    }
+}
+
+template <int DPL>
+__device__ __forceinline__ uint32_t packed_cost(const uint32_t (&w)[packed_words<DPL>()], int j)
+{
+    if constexpr (DPL == 1) return w[0];
+    else return (j & 1) ? w[j >> 1] >> 16 : w[j >> 1] & 0xFFFFu;
+}
+
 // One block of 16 lines of one direction (16 lanes per line, horizontal lines
 // included), fed from the block-cost volume; the next clock's costs are loaded
 // while the current clock computes.
@@ -90,23 +167,25 @@ __device__ __forceinline__ void run_lines_volume(const VolumeArgs &a, const Bloc
             x = xm0 + t * g.dx + xlane;
         }
     };
-    auto load = [&](int t, uint32_t (&c)[DPL]) {
+    constexpr int NP = packed_words<DPL>();
+    auto load = [&](int t, uint32_t (&c)[NP]) {
         int row, x;
         locate(t, row, x);
         row = min(max(row, 0), H - 1);
         x = min(max(x, 0), W - 1);
-        load_u16<DPL>(a.vol + ((size_t)row * W + x) * kDpad + d0, c);
+        load_packed<DPL>(a.vol + ((size_t)row * W + x) * kDpad + d0, c);
     };
 
-    uint32_t Q[DPL], cn[DPL];
+    // costs come through a ring of kRing clocks (packed as loaded), loaded
+    // kRing - 1 clocks ahead: a launch of these lines holds about one wave per
+    // SIMD, so each wave must keep many loads in flight to cover the memory
+    // latency; the clock loop is unrolled over the ring so the slots stay in
+    // fixed registers
+    constexpr int kRing = DPL <= 8 ? 12 : 4;
+    uint32_t Q[DPL], ring[kRing][NP];
 #pragma unroll
     for (int j = 0; j < DPL; ++j) Q[j] = 0;
-    load(0, cn);
-    for (int t = 0; t < g.clocks; ++t) {
-        uint32_t C[DPL];
-#pragma unroll
-        for (int j = 0; j < DPL; ++j) C[j] = cn[j];
-        if (t + 1 < g.clocks) load(t + 1, cn);
+    auto step = [&](int t, const uint32_t (&cw)[NP]) {
         const int s = t - skew;
         int row, x;
         locate(t, row, x);
@@ -117,7 +196,7 @@ __device__ __forceinline__ void run_lines_volume(const VolumeArgs &a, const Bloc
         uint32_t m = 0xFFFFFFFFu;
 #pragma unroll
         for (int j = 0; j < DPL; ++j) {
-            uint32_t c = d0 + j < D ? C[j] : kPadCost;
+            uint32_t c = d0 + j < D ? packed_cost<DPL>(cw, j) : kPadCost;
             c = s < 0 ? 0u : c;  // a line that has not started stays at Q = 0
             const uint32_t qm = j > 0 ? Q[j - 1] : qm_edge;
             const uint32_t qp = j < DPL - 1 ? Q[j + 1] : qp_edge;
@@ -129,7 +208,29 @@ __device__ __forceinline__ void run_lines_volume(const VolumeArgs &a, const Bloc
         for (int j = 0; j < DPL; ++j) Q[j] = L[j] - m;
         const size_t o = active ? ((size_t)row * W + x) * kDpad + d0 : trash;
         store_u16<DPL>(out + o, L);
+    };
+    // clock t sits in slot t % kRing; clocks 0..kRing-2 are loaded up front
+    // and clock t + kRing - 1 while clock t is computed
+    static_for<kRing - 1>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        if (k < g.clocks) load(k, ring[k]);
+    });
+    int t0 = 0;
+    for (; t0 + kRing <= g.clocks; t0 += kRing) {
+        static_for<kRing>([&](auto rc) {
+            constexpr int r = decltype(rc)::value;
+            const int t = t0 + r;
+            // (past the last clock the load is of a clamped, unused position:
+            // unconditional, so every wait counts a fixed number of loads)
+            load(t + kRing - 1, ring[(r + kRing - 1) % kRing]);
+            step(t, ring[r]);
+        });
     }
+    // the last clocks (fewer than kRing), already loaded
+    static_for<kRing - 1>([&](auto rc) {
+        constexpr int r = decltype(rc)::value;
+        if (t0 + r < g.clocks) step(t0 + r, ring[r]);
+    });
 }
 
 template <int DPL>
