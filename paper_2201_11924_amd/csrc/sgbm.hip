@@ -16,74 +16,81 @@ namespace {
 
 // ---------------------------------------------------------------- block costs
 // 16 pixels of one row per 256-thread block, one 16-lane row per pixel, DPL
-// disparities per lane.  The window rows go through LDS one at a time (double
-// buffered, the next row fetched into registers while the current one is
-// summed): the left census words the 16 windows cover and the right words
-// they reach at every disparity, so every sample is an LDS read.
+// disparities per lane.  The window rows come into LDS by direct-to-LDS loads,
+// as many rows at once as fit a 12 KB tile (all of them for blocks up to
+// 14 rows at D <= 128), so a block waits for memory once per tile rather than
+// once per row.  A tile row holds the left census words the 16 windows cover
+// and the right words they reach at every disparity; every sample is an LDS
+// read.
 template <int DPL, bool WIDE>
 __global__ __launch_bounds__(256) void block_cost_kernel(BlockCostArgs a)
 {
     using CW = CensusWord<WIDE>;
     using Word = typename CW::T;
     constexpr int kDpad = kLanesPerLine * DPL;
+    constexpr int kWordDw = (int)sizeof(Word) / 4;
     constexpr int kLeftWords = 16 + 2 * kMaxBlockHalf;
-    constexpr int kRightWords = kLeftWords + kDpad - 1;
-    constexpr int kFetch = (kLeftWords + kRightWords + 255) / 256;
-    __shared__ Word sl[2][kLeftWords], sr[2][kRightWords];
+    constexpr int kRowWords = kLeftWords + kLeftWords + kDpad - 1;  // left slots, then right slots
+    constexpr int kRowDw = kRowWords * kWordDw;
+    constexpr int kFit = 12288 / (kRowDw * 4);
+    constexpr int kRows = kFit < 1 ? 1 : (kFit > 2 * kMaxBlockHalf + 1 ? 2 * kMaxBlockHalf + 1 : kFit);
+    constexpr int kLoads = (kRows * kRowDw + 255) / 256;
+    __shared__ __align__(16) uint32_t tile[kLoads * 256];
     const int tid = threadIdx.x, lane = tid & 15, px = tid >> 4;
     const int W = a.W, H = a.H, y = blockIdx.y, x0 = blockIdx.x * 16, x = x0 + px;
-    const int hw = a.bw / 2, hh = a.bh / 2, d0 = lane * DPL;
+    // lane l sums disparities l, l + 16, l + 32, ...: for each of them the
+    // 16 lanes of a pixel read 16 consecutive right words (no bank conflicts)
+    const int hw = a.bw / 2, hh = a.bh / 2;
     // window columns (clamped to the image) and the right columns they reach;
-    // right word k holds column rlo + k (columns left of the image are never
+    // right slot k holds column rlo + k (columns left of the image are never
     // counted: their samples cost the full bit count)
-    const int xlo = max(x0 - hw, 0), xhi = min(x0 + 15 + hw, W - 1);
-    const int rlo = xlo - (kDpad - 1), nl = xhi - xlo + 1, n = nl + (xhi - rlo + 1);
-    const Word *cl = (const Word *)a.census_l, *cr = (const Word *)a.census_r;
-    auto fetch = [&](int v, Word (&g)[kFetch]) {
-        const size_t row = (size_t)min(max(y + v, 0), H - 1) * W;
-#pragma unroll
-        for (int k = 0; k < kFetch; ++k) {
-            const int i = tid + 256 * k, col = i < nl ? xlo + i : rlo + (i - nl);
-            g[k] = i < n && col >= 0 ? (i < nl ? cl[row + col] : cr[row + col]) : Word(0);
-        }
-    };
-    auto put = [&](int buf, const Word (&g)[kFetch]) {
-#pragma unroll
-        for (int k = 0; k < kFetch; ++k) {
-            const int i = tid + 256 * k;
-            if (i < nl) sl[buf][i] = g[k];
-            else if (i < n) sr[buf][i - nl] = g[k];
-        }
-    };
+    const int xlo = max(x0 - hw, 0), rlo = xlo - (kDpad - 1);
+    const uint32_t *cl = (const uint32_t *)a.census_l, *cr = (const uint32_t *)a.census_r;
     uint32_t acc[DPL];
 #pragma unroll
     for (int j = 0; j < DPL; ++j) acc[j] = 0;
     const int xc = min(x, W - 1);
     const uint32_t bits = (uint32_t)a.bits;
     const bool inner = rlo >= 0;  // no sample reaches left of the image
-    Word g[kFetch];
-    fetch(-hh, g);
-    put(0, g);
-    __syncthreads();
-    for (int v = -hh; v <= hh; ++v) {
-        const int buf = (v + hh) & 1;
-        if (v < hh) fetch(v + 1, g);
-        for (int u = -hw; u <= hw; ++u) {
-            const int cx = min(max(xc + u, 0), W - 1);
-            const Word wl = sl[buf][cx - xlo];
-            const Word *rr = &sr[buf][cx - d0 - rlo];
-            if (inner) {
+    for (int r0 = -hh; r0 <= hh; r0 += kRows) {
+        const int nrows = min(kRows, hh - r0 + 1);
+        if (r0 > -hh) __syncthreads();  // the previous tile's reads are done
 #pragma unroll
-                for (int j = 0; j < DPL; ++j) acc[j] += CW::hamming(wl, rr[-j]);
-            } else {
-#pragma unroll
-                for (int j = 0; j < DPL; ++j) acc[j] += cx - d0 - j >= 0 ? CW::hamming(wl, rr[-j]) : bits;
+        for (int k = 0; k < kLoads; ++k) {
+            const int e = tid + 256 * k;  // dword of the tile
+            if (e < nrows * kRowDw) {
+                const int rr = e / kRowDw, rem = e - rr * kRowDw, idx = rem / kWordDw, h = rem - idx * kWordDw;
+                const int row = min(max(y + r0 + rr, 0), H - 1);
+                const bool left = idx < kLeftWords;
+                const int col = min(max(left ? xlo + idx : rlo + (idx - kLeftWords), 0), W - 1);
+                const uint32_t *src = (left ? cl : cr) + ((size_t)row * W + col) * kWordDw + h;
+                __builtin_amdgcn_global_load_lds(src, &tile[256 * k + (tid & ~63)], 4, 0, 0);
             }
         }
-        if (v < hh) put(buf ^ 1, g);
+        __builtin_amdgcn_s_waitcnt(vmcnt_encoding(0));
         __syncthreads();
+        for (int rr = 0; rr < nrows; ++rr) {
+            const Word *sl = (const Word *)tile + rr * kRowWords, *sr = sl + kLeftWords;
+            for (int u = -hw; u <= hw; ++u) {
+                const int cx = min(max(xc + u, 0), W - 1);
+                const Word wl = sl[cx - xlo];
+                const Word *rp = &sr[cx - lane - rlo];
+                if (inner) {
+#pragma unroll
+                    for (int j = 0; j < DPL; ++j) acc[j] += CW::hamming(wl, rp[-16 * j]);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < DPL; ++j)
+                        acc[j] += cx - lane - 16 * j >= 0 ? CW::hamming(wl, rp[-16 * j]) : bits;
+                }
+            }
+        }
     }
-    if (x < W) store_u16<DPL>(a.vol + ((size_t)y * W + x) * kDpad + d0, acc);
+    if (x < W) {
+        uint16_t *o = a.vol + ((size_t)y * W + x) * kDpad + lane;
+#pragma unroll
+        for (int j = 0; j < DPL; ++j) o[16 * j] = (uint16_t)acc[j];
+    }
 }
 
 // ---------------------------------------------------------------- aggregation
