@@ -188,7 +188,7 @@ __device__ __forceinline__ void run_lines_volume(const VolumeArgs &a, const Bloc
     // SIMD, so each wave must keep many loads in flight to cover the memory
     // latency; the clock loop is unrolled over the ring so the slots stay in
     // fixed registers
-    constexpr int kRing = DPL <= 8 ? 12 : 4;
+    constexpr int kRing = DPL <= 8 ? 12 : 8;
     uint32_t Q[DPL], ring[kRing][NP];
 #pragma unroll
     for (int j = 0; j < DPL; ++j) Q[j] = 0;
