@@ -219,7 +219,8 @@ static int sgbm_aggregation(simsense_handle *h, const void *cl, const void *cr, 
         va.dx[r] = kPathDx[r];
         va.dy[r] = kPathDy[r];
         va.out[r] = (uint16_t *)h->paths[r];
-        va.block_begin[r + 1] = va.block_begin[r] + aggregate_blocks(kPathDx[r], kPathDy[r], p.width, p.height, 16);
+        va.block_begin[r + 1] = va.block_begin[r] + aggregate_blocks(kPathDx[r], kPathDy[r], p.width, p.height,
+                                                                     volume_horizontal_lanes(h->Dpad));
     }
     SS_TRY(launch_aggregate_volume(va, s));
     return SIMSENSE_OK;

@@ -97,6 +97,11 @@ hipError_t launch_post(const PostArgs &a, hipStream_t s);
 // Semi-global block matching: the block-cost volume and the aggregation fed
 // from it (16-bit path values, one block per line block).
 constexpr int kMaxBlockHalf = 15;  // SGBM blocks are at most 31 x 31
+// lanes per horizontal line of the block-cost-fed aggregation
+__host__ __device__ constexpr int volume_horizontal_lanes(int dpad)
+{
+    return dpad == 128 || dpad == 256 ? 64 : dpad == 64 ? 32 : kLanesPerLine;
+}
 struct BlockCostArgs {
     const void *census_l, *census_r;  // uint32 words, or uint64 when bits > 32
     int W, H, bits, bw, bh;

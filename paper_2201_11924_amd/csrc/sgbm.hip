@@ -135,14 +135,14 @@ __device__ __forceinline__ uint32_t packed_cost(const uint32_t (&w)[packed_words
 // One block of 16 lines of one direction (16 lanes per line, horizontal lines
 // included), fed from the block-cost volume; the next clock's costs are loaded
 // while the current clock computes.
-template <int DPL, bool HORIZ>
+template <int DPL, bool HORIZ, int LPL = kLanesPerLine>
 __device__ __forceinline__ void run_lines_volume(const VolumeArgs &a, const BlockGeom &g, uint16_t *out)
 {
-    using LO = LineOps<kLanesPerLine>;
-    constexpr int kDpad = kLanesPerLine * DPL;
+    using LO = LineOps<LPL>;
+    constexpr int kDpad = LPL * DPL;
     const int W = a.W, H = a.H, D = a.D;
-    const int lane = threadIdx.x % kLanesPerLine, li = threadIdx.x / kLanesPerLine;
-    const bool first = lane == 0, last = lane == kLanesPerLine - 1;
+    const int lane = threadIdx.x % LPL, li = threadIdx.x / LPL;
+    const bool first = lane == 0, last = lane == LPL - 1;
     const int d0 = lane * DPL;
     const uint32_t p1 = a.p1, p2 = a.p2;
     const size_t trash = (size_t)W * H * kDpad + d0;
@@ -220,10 +220,9 @@ __device__ __forceinline__ void run_lines_volume(const VolumeArgs &a, const Bloc
     // and clock t + kRing - 1 while clock t is computed
     static_for<kRing - 1>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
-        if (k < g.clocks) load(k, ring[k]);
+        load(k, ring[k]);  // clamped position when k >= clocks
     });
-    int t0 = 0;
-    for (; t0 + kRing <= g.clocks; t0 += kRing) {
+    auto group = [&](int t0) {
         static_for<kRing>([&](auto rc) {
             constexpr int r = decltype(rc)::value;
             const int t = t0 + r;
@@ -232,6 +231,14 @@ __device__ __forceinline__ void run_lines_volume(const VolumeArgs &a, const Bloc
             load(t + kRing - 1, ring[(r + kRing - 1) % kRing]);
             step(t, ring[r]);
         });
+    };
+    // the first group runs ahead of the loop, so the loop is entered with the
+    // loads in flight that each of its iterations leaves (the waits inside it
+    // can then count exactly)
+    int t0 = 0;
+    if (g.clocks >= kRing) {
+        group(0);
+        for (t0 = kRing; t0 + kRing <= g.clocks; t0 += kRing) group(t0);
     }
     // the last clocks (fewer than kRing), already loaded
     static_for<kRing - 1>([&](auto rc) {
@@ -240,16 +247,23 @@ __device__ __forceinline__ void run_lines_volume(const VolumeArgs &a, const Bloc
     });
 }
 
+// Horizontal lines (the longest, W clocks) run with volume_horizontal_lanes()
+// lanes each, so fewer disparities per lane shorten every clock and the launch
+// holds more waves; the other directions keep 16 lanes per line.
 template <int DPL>
 __global__ __launch_bounds__(kBlock) void aggregate_volume_kernel(VolumeArgs a)
 {
+    constexpr int kDpad = kLanesPerLine * DPL;
+    constexpr int kHL = volume_horizontal_lanes(kDpad);
     const int blk = (int)blockIdx.x;
     int dir = 0;
 #pragma unroll
     for (int k = 1; k < 8; ++k)
         if (k < a.ndirs && blk >= a.block_begin[k]) dir = k;
-    const BlockGeom g = block_geometry(a.dx[dir], a.dy[dir], blk - a.block_begin[dir], a.W, a.H, kLinesPerBlock);
-    if (g.kind == 0) run_lines_volume<DPL, true>(a, g, a.out[dir]);
+    const bool horiz = a.dy[dir] == 0;
+    const BlockGeom g = block_geometry(a.dx[dir], a.dy[dir], blk - a.block_begin[dir], a.W, a.H,
+                                       horiz ? kBlock / kHL : kLinesPerBlock);
+    if (horiz) run_lines_volume<kDpad / kHL, true, kHL>(a, g, a.out[dir]);
     else run_lines_volume<DPL, false>(a, g, a.out[dir]);
 }
 

@@ -213,6 +213,8 @@ def test_full_right_reference_lr_matches_oracle(orc, nat, W, H, D, paths, kw):
     # 62-bit census words; the largest block (31 x 31) with the window wider than a tile
     (80, 37, 48, dict(census_mode=1, block_w=3, block_h=3, p1=40, p2=500)),
     (70, 40, 64, dict(census_w=3, census_h=3, census_mode=1, block_w=31, block_h=31, p1=20, p2=400)),
+    # D = 128: horizontal lines with 64 lanes of 2 disparities
+    (150, 50, 128, dict(block_w=3, block_h=3, p1=30, p2=300)),
 ])
 def test_sgbm_matches_oracle(orc, nat, W, H, D, kw):
     """Semi-global block matching (block-summed Hamming cost, 16-bit path values)
