@@ -7,7 +7,8 @@
 // fastest, the path buffers' layout); aggregate_volume_kernel runs the path
 // recurrence of every scanline of every direction from that volume.  The
 // recurrence, the line layout of a block and the cross-lane steps are those of
-// the census-fed aggregation; only the cost source and the value width differ.
+// the census-fed aggregation; the cost source, the value width and the load
+// schedule differ.
 #include "aggregate_impl.h"
 
 namespace ss {
@@ -16,7 +17,8 @@ namespace {
 
 // ---------------------------------------------------------------- block costs
 // 16 pixels of one row per 256-thread block, one 16-lane row per pixel, DPL
-// disparities per lane.  The window rows come into LDS by direct-to-LDS loads,
+// disparities per lane (lane l: l, l + 16, l + 32, ...).  The window rows come
+// into LDS by direct-to-LDS loads,
 // as many rows at once as fit a 12 KB tile (all of them for blocks up to
 // 14 rows at D <= 128), so a block waits for memory once per tile rather than
 // once per row.  A tile row holds the left census words the 16 windows cover
@@ -132,9 +134,9 @@ __device__ __forceinline__ uint32_t packed_cost(const uint32_t (&w)[packed_words
     else return (j & 1) ? w[j >> 1] >> 16 : w[j >> 1] & 0xFFFFu;
 }
 
-// One block of 16 lines of one direction (16 lanes per line, horizontal lines
-// included), fed from the block-cost volume; the next clock's costs are loaded
-// while the current clock computes.
+// The lines of one block of one direction (LPL lanes per line, kBlock / LPL
+// lines), fed from the block-cost volume; the costs of a clock are loaded
+// several clocks ahead (the ring below).
 template <int DPL, bool HORIZ, int LPL = kLanesPerLine>
 __device__ __forceinline__ void run_lines_volume(const VolumeArgs &a, const BlockGeom &g, uint16_t *out)
 {
