@@ -38,7 +38,9 @@ typedef enum simsense_status {
     SIMSENSE_ERR_OUT_OF_MEMORY = -3,    /* device allocation failed */
     SIMSENSE_ERR_DEVICE = -4,           /* a HIP runtime call or kernel launch failed */
     SIMSENSE_ERR_UNSUPPORTED = -5,      /* valid but not supported by this build */
-    SIMSENSE_ERR_ABI = -6               /* struct_size does not match this library */
+    SIMSENSE_ERR_ABI = -6,              /* struct_size does not match this library */
+    SIMSENSE_ERR_TOO_LARGE = -7         /* the parameters need more scratch than
+                                           simsense_compute_noalloc's static buffer holds */
 } simsense_status;
 
 /*
@@ -373,6 +375,23 @@ int simsense_get_tuning(const simsense_handle *h, simsense_batch_tuning *t);
  * fastest and returns it in *best.  Synchronous. */
 int simsense_autotune(simsense_handle *h, const uint8_t *left, const uint8_t *right, int32_t pitch, int32_t reps,
                       simsense_batch_tuning *best, float *ms, int32_t max_candidates, int32_t *count, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): simsense_compute without
+ * a handle.  Same arguments and results as simsense_create + simsense_compute +
+ * simsense_destroy with `params` (bit for bit: the same kernels, the aggregation
+ * launched one block per line block), but the scratch lives in one static device
+ * array of SIMSENSE_NOALLOC_SCRATCH_BYTES per GPU, which the library holds from
+ * its first call on that GPU until the process ends; the call allocates nothing.
+ * Parameters whose scratch (simsense_scratch_bytes) exceeds it return
+ * SIMSENSE_ERR_TOO_LARGE before anything is enqueued (64 MiB holds, for example,
+ * 320x240 with D = 64 and 8 paths, or 640x480 with D = 64 and 2 paths).  Every
+ * call on one GPU shares that GPU's array: calls that overlap in time on one GPU
+ * (on different streams, or from different threads) race and must not be issued;
+ * calls queued in order on one stream are safe.  Asynchronous on `stream`. */
+#define SIMSENSE_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int simsense_compute_noalloc(const simsense_params *params, const uint8_t *left, const uint8_t *right,
+                             int32_t pitch, float *depth, float *disp, uint8_t *flags, void *stream);
 
 /* Human-readable name of a status code (static storage). */
 const char *simsense_strerror(int status);

@@ -30,7 +30,7 @@ int census_bits(int cw, int ch, int mode)
 
 int path_lines(int dx, int dy, int W, int H) { return dy == 0 ? H : (dx == 0 ? W : W + H - 1); }
 
-static int validate(const simsense_params *p)
+int validate(const simsense_params *p)
 {
     if (!p) return SIMSENSE_ERR_NULL_POINTER;
     if (p->struct_size != sizeof(simsense_params)) return SIMSENSE_ERR_ABI;
@@ -59,15 +59,9 @@ static int validate(const simsense_params *p)
     return SIMSENSE_OK;
 }
 
-struct Layout {
-    size_t census, paths, per_px[7], total;
-    bool right_run;  // lr_mode 1: two more census maps and a second per-pixel set
-    size_t volume;   // SGBM: the block-cost volume (16-bit, d fastest)
-};
-
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-static Layout layout(const simsense_params *p)
+Layout layout(const simsense_params *p)
 {
     Layout l{};
     const size_t npx = (size_t)p->width * p->height;
@@ -86,6 +80,49 @@ static Layout layout(const simsense_params *p)
         l.total += sets * l.per_px[i];
     }
     return l;
+}
+
+// The handle's parameter-derived fields (no device work).
+void init_handle(simsense_handle *h, const simsense_params *params)
+{
+    h->p = *params;
+    h->bits = census_bits(params->census_w, params->census_h, params->census_mode);
+    h->wide = h->bits > 32;
+    h->Dpad = padded_disp(params->max_disp);
+    h->hlanes = horizontal_lanes(h->Dpad);
+    h->ndirs = params->num_paths;
+    h->sgbm = params->block_w * params->block_h > 1;
+}
+
+// Points the handle's buffers into one block of scratch laid out by layout().
+void carve_scratch(simsense_handle *h, uint8_t *base, const Layout &l)
+{
+    uint8_t *cur = base;
+    h->census_l = cur; cur += l.census;
+    h->census_r = cur; cur += l.census;
+    for (int r = 0; r < h->ndirs; ++r) { h->paths[r] = cur; cur += l.paths; }
+    h->disp_int = cur; cur += l.per_px[0];
+    h->cost_best = (uint16_t *)cur; cur += l.per_px[1];
+    h->cost_second = (uint16_t *)cur; cur += l.per_px[2];
+    h->disp_right = cur; cur += l.per_px[3];
+    h->disp_sub = (float *)cur; cur += l.per_px[4];
+    h->masked = (float *)cur; cur += l.per_px[5];
+    h->flags_pre = cur; cur += l.per_px[6];
+    if (l.volume) {
+        h->volume = (uint16_t *)cur;
+        cur += l.volume;
+    }
+    if (l.right_run) {
+        h->census_ml = cur; cur += l.census;
+        h->census_mr = cur; cur += l.census;
+        h->disp_int_m = cur; cur += l.per_px[0];
+        h->cost_best_m = (uint16_t *)cur; cur += l.per_px[1];
+        h->cost_second_m = (uint16_t *)cur; cur += l.per_px[2];
+        h->disp_right_m = cur; cur += l.per_px[3];
+        h->disp_sub_m = (float *)cur; cur += l.per_px[4];
+        h->masked_m = (float *)cur; cur += l.per_px[5];
+        h->flags_m = cur; cur += l.per_px[6];
+    }
 }
 
 }  // namespace ss
@@ -363,6 +400,7 @@ const char *simsense_strerror(int status)
     case SIMSENSE_ERR_DEVICE: return "HIP runtime or kernel launch error";
     case SIMSENSE_ERR_UNSUPPORTED: return "unsupported configuration";
     case SIMSENSE_ERR_ABI: return "struct_size mismatch (ABI)";
+    case SIMSENSE_ERR_TOO_LARGE: return "scratch needed exceeds the no-allocation entry point's static buffer";
     default: return "unknown status";
     }
 }
@@ -382,13 +420,7 @@ int simsense_create(const simsense_params *params, simsense_handle **out)
     Layout l = layout(params);
     simsense_handle *h = new (std::nothrow) simsense_handle();
     if (!h) return SIMSENSE_ERR_OUT_OF_MEMORY;
-    h->p = *params;
-    h->bits = census_bits(params->census_w, params->census_h, params->census_mode);
-    h->wide = h->bits > 32;
-    h->Dpad = padded_disp(params->max_disp);
-    h->hlanes = horizontal_lanes(h->Dpad);
-    h->ndirs = params->num_paths;
-    h->sgbm = params->block_w * params->block_h > 1;
+    init_handle(h, params);
     if (hipDeviceGetAttribute(&h->num_cus, hipDeviceAttributeMultiprocessorCount, 0) != hipSuccess) {
         (void)hipGetLastError();
         h->num_cus = 256;
@@ -402,32 +434,7 @@ int simsense_create(const simsense_params *params, simsense_handle **out)
         return SIMSENSE_ERR_OUT_OF_MEMORY;
     }
     h->d_args_m = h->d_args + 1;
-    uint8_t *cur = (uint8_t *)h->block;
-    h->census_l = cur; cur += l.census;
-    h->census_r = cur; cur += l.census;
-    for (int r = 0; r < h->ndirs; ++r) { h->paths[r] = cur; cur += l.paths; }
-    h->disp_int = cur; cur += l.per_px[0];
-    h->cost_best = (uint16_t *)cur; cur += l.per_px[1];
-    h->cost_second = (uint16_t *)cur; cur += l.per_px[2];
-    h->disp_right = cur; cur += l.per_px[3];
-    h->disp_sub = (float *)cur; cur += l.per_px[4];
-    h->masked = (float *)cur; cur += l.per_px[5];
-    h->flags_pre = cur; cur += l.per_px[6];
-    if (l.volume) {
-        h->volume = (uint16_t *)cur;
-        cur += l.volume;
-    }
-    if (l.right_run) {
-        h->census_ml = cur; cur += l.census;
-        h->census_mr = cur; cur += l.census;
-        h->disp_int_m = cur; cur += l.per_px[0];
-        h->cost_best_m = (uint16_t *)cur; cur += l.per_px[1];
-        h->cost_second_m = (uint16_t *)cur; cur += l.per_px[2];
-        h->disp_right_m = cur; cur += l.per_px[3];
-        h->disp_sub_m = (float *)cur; cur += l.per_px[4];
-        h->masked_m = (float *)cur; cur += l.per_px[5];
-        h->flags_m = cur; cur += l.per_px[6];
-    }
+    carve_scratch(h, (uint8_t *)h->block, l);
     h->last_stream = nullptr;
     h->profiling = false;
     h->prof_events = nullptr;

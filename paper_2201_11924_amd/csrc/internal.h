@@ -169,6 +169,20 @@ hipError_t launch_volume_sum(const PathSet &paths, int ndirs, bool values16, int
                              uint16_t *out, hipStream_t s);
 
 // ---------------------------------------------------------------- handle
+// Parameter validation (a simsense_status) and the handle's scratch layout: one
+// block holding the census maps, the per-direction path values, the per-pixel
+// results (and for lr_mode 1 a second set; for SGBM the block-cost volume),
+// every piece 256-byte aligned.
+int validate(const simsense_params *p);
+struct Layout {
+    size_t census, paths, per_px[7], total;
+    bool right_run;  // lr_mode 1: two more census maps and a second per-pixel set
+    size_t volume;   // SGBM: the block-cost volume (16-bit, d fastest)
+};
+Layout layout(const simsense_params *p);
+// fields derived from the parameters; the buffers carved from `base` (l.total bytes)
+void init_handle(simsense_handle *h, const simsense_params *params);
+void carve_scratch(simsense_handle *h, uint8_t *base, const Layout &l);
 // Work common to the compute entry points; each returns a simsense_status.
 //  enqueue_match: census, aggregation and selection into the handle's scratch
 //                 (d*, S1, S2, dR, sub-pixel, masked disparity, flags bits 0..2);

@@ -23,7 +23,8 @@ _lib = ct.CDLL(LIB_PATH)
 
 OK = 0
 STATUS = {0: "ok", -1: "invalid argument", -2: "null pointer", -3: "out of memory", -4: "device error",
-          -5: "unsupported", -6: "abi mismatch"}
+          -5: "unsupported", -6: "abi mismatch", -7: "too large for the static scratch"}
+ERR_TOO_LARGE = -7
 FLAG_UNIQUE, FLAG_LR, FLAG_NONZERO, FLAG_VALID = 1, 2, 4, 8
 
 PARAM_FIELDS = ("width", "height", "max_disp", "census_w", "census_h", "census_mode", "p1", "p2",
@@ -66,6 +67,7 @@ _lib.simsense_strerror.argtypes = [ct.c_int]
 _lib.simsense_strerror.restype = ct.c_char_p
 _lib.simsense_scratch_bytes.argtypes = [ct.POINTER(Params)]
 _lib.simsense_scratch_bytes.restype = _i64
+_lib.simsense_compute_noalloc.argtypes = [ct.POINTER(Params), _vp, _vp, _i32, _vp, _vp, _vp, _vp]
 _lib.simsense_profile_enable.argtypes = [_vp, ct.c_int]
 _lib.simsense_profile_read.argtypes = [_vp, ct.POINTER(ct.c_double), ct.POINTER(_i32), _i32]
 PASSES = ("census", "aggregate", "select", "post")
@@ -213,6 +215,26 @@ class SimSense:
         _check(_lib.simsense_compute_ex(self._h, _ptr(left), _ptr(right), W, ct.byref(o), _stream(stream)),
                "simsense_compute_ex")
         return out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def compute_noalloc(params: Dict, left: torch.Tensor, right: torch.Tensor, depth: torch.Tensor,
+                    disp: Optional[torch.Tensor] = None, flags: Optional[torch.Tensor] = None, stream=None) -> None:
+    """simsense_compute_noalloc: the whole path without a handle, in the library's
+    static per-GPU scratch (no device allocation)."""
+    H, W = params["height"], params["width"]
+    _need(left, torch.uint8, (H, W), "left")
+    _need(right, torch.uint8, (H, W), "right")
+    _need(depth, torch.float32, (H, W), "depth")
+    if disp is not None:
+        _need(disp, torch.float32, (H, W), "disp")
+    if flags is not None:
+        _need(flags, torch.uint8, (H, W), "flags")
+    p = Params.from_dict(params)
+    _check(_lib.simsense_compute_noalloc(ct.byref(p), _ptr(left), _ptr(right), W, _ptr(depth), _ptr(disp),
+                                         _ptr(flags), _stream(stream)), "simsense_compute_noalloc")
 
 
 def ir_noise(img: torch.Tensor, gamma: torch.Tensor, n: torch.Tensor, out: Optional[torch.Tensor] = None,

@@ -75,3 +75,17 @@ def test_scratch_bytes_scale(nat):
     p = dict(base_params(), width=1280, height=720, max_disp=128)
     b = nat.scratch_bytes(p)
     assert 8 * 1280 * 720 * 128 <= b < 8 * 1280 * 720 * 128 + 40 * 1280 * 720
+
+
+def test_noalloc_host_checks(nat):
+    # argument errors and the scratch limit are reported before any device work
+    lib = nat.lib()
+    big = nat.Params.from_dict(dict(base_params(), width=1280, height=720, max_disp=128))
+    fake = ct.c_void_p(256)
+    assert lib.simsense_compute_noalloc(ct.byref(big), fake, fake, 1280, fake, None, None, None) == nat.ERR_TOO_LARGE
+    assert lib.simsense_compute_noalloc(ct.byref(big), None, None, 1280, None, None, None, None) == -2
+    bad = nat.Params.from_dict(dict(base_params(), num_paths=3))
+    assert lib.simsense_compute_noalloc(ct.byref(bad), fake, fake, 320, fake, None, None, None) == -1
+    small = nat.Params.from_dict(base_params())
+    assert lib.simsense_compute_noalloc(ct.byref(small), fake, fake, 100, fake, None, None, None) == -1
+    assert nat.scratch_bytes(base_params()) <= nat.NOALLOC_SCRATCH_BYTES
