@@ -20,13 +20,18 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# algorithmic work of the aggregation pass per (pixel, disparity, path):
-# XOR + popcount for the matching cost, then min(d-1, d+1), +P1, min with L(d),
-# min with P2, +C, -m and the running minimum of the path minimum m.
-AGG_OPS_PER_PDR = 9
-# MI355X: 256 CUs x 64 32-bit VALU lanes per clock x 2.4 GHz
+# algorithmic work of the aggregation pass per (pixel, disparity, path), the
+# recurrence's own operations: min(L(d-1), L(d+1)), +P1, min with L(d), min with
+# m + P2, +C, -m, the share of the path minimum m, and the accumulation into the
+# summed cost (the cost itself, XOR + popcount, is not counted)
+AGG_OPS_PER_PDR = 8
+# MI355X: 256 CUs x 64 32-bit VALU lanes per clock x 2.4 GHz; packed 16-bit
+# instructions do two lane-operations each
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
+VALU_PEAK_OPS_PACKED16 = 2 * VALU_PEAK_OPS
 HBM_PEAK = 8.0e12
+# the machine's CPU share for one GPU (worker pools are sized to it)
+HOST_POOL_MAX = 16
 
 
 def parse():
@@ -82,18 +87,78 @@ def measured_traffic():
         return None
 
 
-def cpu_baseline(params, left, right, rows):
-    """The oracle as it stands, one host thread, on a bounded sample of the workload."""
+def _oracle_pair(job):
+    """One pair through the oracle (noise .. depth); returns the seconds it took."""
     from oracle import oracle as orc
+    params, raw = job
+    t0 = time.perf_counter()
+    L = orc.ir_noise(raw[0], raw[2], raw[3])
+    R = orc.ir_noise(raw[1], raw[4], raw[5])
+    orc.sgm(params, L, R)
+    return time.perf_counter() - t0
+
+
+def _load_oracle(_):
+    from oracle import oracle as orc
+    orc.lib()
+
+
+def _pool_rate(jobs, workers):
+    """Pairs per second of the oracle over `jobs` on `workers` host processes
+    (dynamic scheduling, one pair per task); wall clock of the whole map."""
+    from multiprocessing import get_context
+    with get_context("spawn").Pool(workers) as pool:
+        pool.map(_load_oracle, range(workers), chunksize=1)  # start-up and oracle load, untimed
+        t0 = time.perf_counter()
+        pool.map(_oracle_pair, jobs, chunksize=1)
+        wall = time.perf_counter() - t0
+    return len(jobs) / wall, wall
+
+
+def cpu_baseline(params, left, right, rows, workers):
+    """The oracle as it stands on the host: single-threaded legs on one pair of
+    the 320x240 and 1280x720 workloads, and all-cores legs (one process per core,
+    pairs spread over them) on the uneven 64-pair batch and on 16 sensor pairs."""
+    from oracle import oracle as orc
+    from synth import CONFIGS, pair_seed
+    from synth.stereo import sensor_like
     orc.build(force=False)
+    legs = {}
     p = dict(params, height=rows)
     t0 = time.perf_counter()
     orc.sgm(p, np.ascontiguousarray(left[:rows]), np.ascontiguousarray(right[:rows]))
     dt = time.perf_counter() - t0
-    frac = rows / params["height"]
-    return {"value": round(frac / dt, 6), "unit": "pairs/s", "cores": 1, "kind": "oracle",
-            "sample": f"{rows} of 720 rows of one 1280x720 D=128 8-path pair (full path, census..depth), "
-                      f"{dt:.2f} s single-threaded, scaled to pairs/s"}
+    legs["pair_1280x720_d128_1thread"] = {"pairs_s": round(rows / params["height"] / dt, 5), "cores": 1,
+                                           "sample": f"{rows} of 720 rows, census..depth, {dt:.2f} s"}
+    c0 = CONFIGS["pair_320x240_d64"]
+    raw0 = _pool_generate([(c0["spec"], pair_seed(0, 0))], 1)[0]
+    ts = sorted(_oracle_pair((c0["params"], raw0)) for _ in range(5))
+    legs["pair_320x240_d64_1thread"] = {"pairs_s": round(1.0 / ts[2], 4), "cores": 1,
+                                         "sample": "one pair, noise..depth, median of 5 runs"}
+    shapes = [(320, 240, 64), (640, 480, 96), (848, 480, 128), (1280, 720, 128)]
+    specs, plist = [], []
+    for si, (w, h, d) in enumerate(shapes):
+        c = sensor_like(w, h, d)
+        for i in range(16):
+            specs.append((c["spec"], pair_seed(2, 16 * si + i)))
+            plist.append(c["params"])
+    raws = _pool_generate(specs, workers)
+    rate, wall = _pool_rate(list(zip(plist, raws)), workers)
+    work = sum(q["width"] * q["height"] * q["max_disp"] for q in plist)
+    legs["batch_64_uneven_all_cores"] = {"pairs_s": round(rate, 4), "cores": workers, "wall_s": round(wall, 2),
+                                         "mpix_disp_per_s": round(work / wall / 1e6, 2),
+                                         "sample": "the whole 64-pair batch, noise..depth per pair"}
+    c1 = CONFIGS["pair_1280x720_d128"]
+    raws = _pool_generate([(c1["spec"], pair_seed(4, i)) for i in range(16)], workers)
+    rate, wall = _pool_rate([(c1["params"], r) for r in raws], workers)
+    legs["sensor_16_pairs_all_cores"] = {"pairs_s": round(rate, 4), "cores": workers, "wall_s": round(wall, 2),
+                                         "sample": "16 of the 256 sensor pairs (32 cameras x 8 steps), plain "
+                                                   "8-path, noise..depth per pair"}
+    return {"value": legs["sensor_16_pairs_all_cores"]["pairs_s"], "unit": "pairs/s", "cores": workers,
+            "host_cores": os.cpu_count(), "kind": "oracle",
+            "sample": f"16 1280x720 D=128 8-path pairs (the headline shape), one oracle process per core on "
+                      f"{workers} of the host's {os.cpu_count()} cores, noise..depth, wall clock",
+            "legs": legs}
 
 
 def _pool_generate(spec_seeds, workers):
@@ -347,9 +412,6 @@ def main():
 
     for _ in range(args.warmup):
         step()
-    torch.cuda.synchronize()
-    ss.profile(True)
-    ss.profile_read()
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -360,9 +422,20 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_total = start.elapsed_time(end)
+    ms_step = ms_total / args.steps
+    # per-pass device times: the same steps again, with the library's per-pass
+    # HIP events recorded on the launch stream around each pass
+    ss.profile(True)
+    ss.profile_read()
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(args.steps):
+        step()
+    end.record()
+    torch.cuda.synchronize()
+    ms_step_profiled = start.elapsed_time(end) / args.steps
     calls, pass_ms = ss.profile_read()
     ss.profile(False)
-    ms_step = ms_total / args.steps
     pairs_s = 1000.0 / ms_step
     vol = W * H * D
 
@@ -370,10 +443,16 @@ def main():
     agg_ops = AGG_OPS_PER_PDR * P * vol
     achieved = agg_ops / agg_s
     kernel = "aggregate_queue_kernel" if ss.get_tuning()["blocks_per_cu"] > 0 else "aggregate_kernel"
+    # the kernel's path arithmetic runs in 32-bit lanes, so its peak is the
+    # 32-bit one; the packed 16-bit peak (what a u16 form could reach) is beside it
     roofline = {"kernel": kernel, "bound": "alu", "achieved": round(achieved / 1e12, 3),
                 "peak": round(VALU_PEAK_OPS / 1e12, 3), "unit": "Tops/s", "frac": round(achieved / VALU_PEAK_OPS, 4),
                 "traffic": measured_traffic(),
-                "ops_per_launch": agg_ops, "avg_launch_us": round(agg_s * 1e6, 2)}
+                "peak_packed_u16": round(VALU_PEAK_OPS_PACKED16 / 1e12, 3),
+                "frac_packed_u16": round(achieved / VALU_PEAK_OPS_PACKED16, 4),
+                "ops_per_pixel_disp_path": AGG_OPS_PER_PDR,
+                "ops_per_launch": agg_ops, "avg_launch_us": round(agg_s * 1e6, 2),
+                "timed_by": "library per-pass HIP events on the launch stream, second timed loop of the same steps"}
     # floors of the whole step: with 8 paths the summed costs cannot stay on
     # chip, so at least one uint16 write and read of W*H*D values, plus the two
     # images in and depth, disparity and flags out; and the aggregation's
@@ -397,6 +476,7 @@ def main():
                    "width": W, "height": H, "max_disp": D, "num_paths": P},
         "mpix_disp_per_s": round(vol * pairs_s / 1e6, 1),
         "pass_us": {k: round(v / calls * 1000.0, 2) for k, v in pass_ms.items()},
+        "ms_per_step_with_pass_events": round(ms_step_profiled, 5),
         "wall_s": round(wall, 3),
         "roofline": roofline,
         "step_floors": floors,
@@ -433,7 +513,8 @@ def main():
         from oracle import oracle as orc
         Lh = orc.ir_noise(pair.left, pair.gamma_l, pair.n_l)
         Rh = orc.ir_noise(pair.right, pair.gamma_r, pair.n_r)
-        out["cpu_baseline"] = cpu_baseline(params, Lh, Rh, args.cpu_sample_rows)
+        workers = max(1, min(HOST_POOL_MAX, os.cpu_count() or 1))
+        out["cpu_baseline"] = cpu_baseline(params, Lh, Rh, args.cpu_sample_rows, workers)
     print(json.dumps(out))
 
 

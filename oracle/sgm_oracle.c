@@ -228,8 +228,8 @@ void orc_cost_right(const uint64_t *cl, const uint64_t *cr, int W, int H, int D,
             }
 }
 
-/* Semi-global block matching cost (Sec. VI-D: the Hamming distance between the
- * local regions of the two pixels): the pixel costs summed over a bw x bh block
+/* Semi-global block matching cost (Sec. VI-D, the block-based cost mode, which
+ * compares the neighbourhoods around the two pixels): the pixel costs summed over a bw x bh block
  * centred on the pixel, block samples outside the image clamped to the edge,
  *   CB(x,y,d) = sum_{|u|<=bw/2, |v|<=bh/2} C(clamp(x+u), clamp(y+v), d). */
 void orc_block_cost(const uint16_t *C, int W, int H, int D, int bw, int bh, uint16_t *CB)

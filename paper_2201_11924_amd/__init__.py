@@ -6,10 +6,10 @@ thin ctypes binding.  Importing the binding without a built library raises.
 """
 import importlib
 
-__all__ = ["native", "build"]
+__all__ = ["native", "build", "train", "workloads"]
 
 
 def __getattr__(name):
-    if name in ("native", "build", "learned", "batch"):
+    if name in ("native", "build", "train", "workloads"):
         return importlib.import_module(f"{__name__}.{name}")
     raise AttributeError(name)

@@ -1,6 +1,6 @@
-// Semi-global block matching (Sec. VI-D: the matching cost of two pixels is the
-// Hamming distance between their local regions): the census Hamming costs
-// summed over a block centred on the pixel (samples clamped to the image),
+// Semi-global block matching (Sec. VI-D, the block-based cost mode: two pixels
+// are compared through the neighbourhoods around them): the census Hamming
+// costs summed over a block centred on the pixel (samples clamped to the image),
 // aggregated by the same SGM recurrence with 16-bit path values.
 //
 // Two kernels: block_cost_kernel writes the block-cost volume (16-bit, d
