@@ -244,7 +244,7 @@ typedef struct simsense_net simsense_net; /* opaque */
 int64_t simsense_net_num_params(void);
 
 /* Allocates a net for up to `max_pixels` = batch * height * width pixels per call
- * (about 360 bytes of device memory per pixel) with He-uniform weights drawn from
+ * (about 450 bytes of device memory per pixel) with He-uniform weights drawn from
  * `seed` and zero biases; Adam state zero.  Synchronous. */
 int simsense_net_create(int64_t max_pixels, uint64_t seed, simsense_net **out);
 int simsense_net_destroy(simsense_net *net);
@@ -258,6 +258,22 @@ int simsense_net_set_state(simsense_net *net, const float *params, const float *
                            int64_t count, int64_t step);
 /* HOST buffer: the gradient computed by the last training step. */
 int simsense_net_get_grads(simsense_net *net, float *grads, int64_t count);
+/* Tensors the last simsense_net_forward or simsense_net_train_step left in the
+ * net, copied to a HOST buffer of exactly `bytes` (waits for the net's last
+ * stream); for checking the layers one by one.  P = batch * height * width of
+ * that call, NHWC pixel order:
+ *   SIMSENSE_NET_ACTIVATION, layer 0..2: bf16 [P][32], layer l's output after its
+ *     ReLU (the input of layer l + 1);
+ *   SIMSENSE_NET_OUTPUT, layer 3: fp32 [P][2], residual and logit;
+ *   SIMSENSE_NET_OUTPUT_GRAD (training step only), layer 3: bf16 [P][16], the loss
+ *     gradient at the net output in channels 0 and 1 (the rest 0); layer 0..2:
+ *     bf16 [P][32], the gradient at layer l's pre-activation output (the
+ *     backward-data result times the ReLU derivative).
+ * Returns SIMSENSE_ERR_INVALID_ARGUMENT for another (what, layer) or size. */
+#define SIMSENSE_NET_ACTIVATION 0
+#define SIMSENSE_NET_OUTPUT 1
+#define SIMSENSE_NET_OUTPUT_GRAD 2
+int simsense_net_read_tensor(simsense_net *net, int32_t what, int32_t layer, void *host, int64_t bytes);
 
 /* Forward pass.  `features`: bf16 [batch][height][width][8] (device); `out`: fp32
  * [batch][height][width][2] (device): residual, logit. */
@@ -348,6 +364,26 @@ int simsense_batch_compute(simsense_batch *b, const simsense_pair *pairs, void *
  * large.  The graph is kept for one (net, tau, uncertain) triple. */
 int simsense_batch_learned_compute(simsense_batch *b, simsense_net *net, const simsense_pair *pairs, float tau,
                                    unsigned *uncertain, void *stream);
+/* The learned form with plain SGM as its fallback: simsense_batch_learned_compute
+ * on every pair, then for each pair that falls back, simsense_compute with the
+ * `plain` handle (normally the same parameters with num_paths = 8) on the same
+ * images, writing the pair's own depth / disp / flags over the learned result.
+ * `plain` must have the slots' width, height and max_disp (it may be NULL with
+ * mode NEVER).  Modes:
+ *   SIMSENSE_FALLBACK_THRESHOLD  pairs whose count of pixels with a logit within
+ *                                (-tau, tau) exceeds max_uncertain_frac (0..1) of
+ *                                their pixels; the counts are copied to the host,
+ *                                so the call waits once for the learned pass;
+ *   SIMSENSE_FALLBACK_NEVER      none (the learned result stands; no wait);
+ *   SIMSENSE_FALLBACK_ALWAYS     every pair (no wait).
+ * `fell_back` (host, nullable, n entries) receives 1 for pairs recomputed, else 0.
+ * The plain runs are enqueued on `stream` after the learned pass. */
+#define SIMSENSE_FALLBACK_THRESHOLD 0
+#define SIMSENSE_FALLBACK_NEVER 1
+#define SIMSENSE_FALLBACK_ALWAYS 2
+int simsense_batch_learned_fallback(simsense_batch *b, simsense_net *net, simsense_handle *plain,
+                                    const simsense_pair *pairs, float tau, unsigned *uncertain, int32_t mode,
+                                    float max_uncertain_frac, int32_t *fell_back, void *stream);
 int simsense_batch_set_tuning(simsense_batch *b, const simsense_batch_tuning *t);
 int simsense_batch_get_tuning(const simsense_batch *b, simsense_batch_tuning *t);
 /* Times every tuning candidate (horizontal_lanes in {16, 32, 64} x blocks_per_cu in

@@ -1,7 +1,10 @@
 """CPU oracle of the learned surrogate (a small convolutional net on 2-path SGM features).
 
 TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
-benchmark's CPU-baseline leg, never by the GPU library.  Plain numpy in fp64.
+benchmark's CPU-baseline leg, never by the GPU library.  Plain numpy in fp64;
+the features and the final combination can instead be evaluated in float32, the
+precision in which the kernels take the decisions that follow them (a bf16
+rounding, a validity test).
 
 The net (not part of the paper; it stands in for six of the eight SGM paths):
 four 3x3 convolutions with zero padding, 4 -> 32 -> 32 -> 32 -> 2 channels, ReLU
@@ -138,15 +141,24 @@ def adam_step(p: np.ndarray, g: np.ndarray, m: np.ndarray, v: np.ndarray, step: 
     p -= lr * mh / (np.sqrt(vh) + eps)
 
 
-def features(ir: np.ndarray, s1: np.ndarray, s2: np.ndarray, dint: np.ndarray, max_disp: int, smax: float):
+def features(ir: np.ndarray, s1: np.ndarray, s2: np.ndarray, dint: np.ndarray, max_disp: int, smax: float,
+             dtype=np.float64):
     """The net's four input channels from a 2-path result: IR/255, S1/Smax, S2/Smax
-    (1 where no second candidate exists) and d*/D."""
-    s2f = np.where(s2 < 0, smax, s2).astype(np.float64)
-    return np.stack([ir / 255.0, s1 / smax, np.minimum(s2f, smax) / smax, dint / float(max_disp)], axis=-1)
+    (1 where no second candidate exists) and d*/D.  Each channel is one quotient;
+    with dtype=np.float32 it is the correctly rounded float32 quotient, so that the
+    bf16 rounding of a feature (a quantisation decision) is taken from the same
+    float32 value the kernel rounds."""
+    f = lambda a: np.asarray(a).astype(dtype)
+    s2f = np.minimum(np.where(np.asarray(s2) < 0, smax, s2), smax)
+    sm = dtype(smax)
+    return np.stack([f(ir) / dtype(255.0), f(s1) / sm, f(s2f) / sm, f(dint) / dtype(max_disp)], axis=-1)
 
 
-def combine(d2_sub: np.ndarray, out: np.ndarray) -> np.ndarray:
+def combine(d2_sub: np.ndarray, out: np.ndarray, dtype=np.float64) -> np.ndarray:
     """Disparity of the learned form before the median: d2 + residual where the
-    logit is positive and the sum is positive, else 0 (invalid)."""
-    d = d2_sub + out[..., 0]
-    return np.where((out[..., 1] > 0) & (d > 0), d, 0.0)
+    logit is positive and the sum is positive, else 0 (invalid).  With
+    dtype=np.float32 the sum and the validity decision are taken in float32 (the
+    kernel's precision) from float32 inputs."""
+    d2, r, z = (np.asarray(a).astype(dtype) for a in (d2_sub, out[..., 0], out[..., 1]))
+    d = d2 + r
+    return np.where((z > 0) & (d > 0), d, dtype(0.0))

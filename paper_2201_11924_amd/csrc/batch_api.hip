@@ -51,6 +51,7 @@ struct simsense_batch {
     CensusJob *h_cjobs[2];
     PostArgs *h_post[2];
     hipEvent_t staged[2];
+    unsigned *h_uncertain;  // pinned: the learned form's per-pair counts, read back for the fallback
     int stage_idx;
     // launch plan
     struct AggGroup { int dpad, hl; bool wide; size_t item_off; int nitems; int counter; };
@@ -408,6 +409,7 @@ void free_batch(simsense_batch *b)
         if (b->h_cjobs[i]) (void)hipHostFree(b->h_cjobs[i]);
         if (b->h_post[i]) (void)hipHostFree(b->h_post[i]);
     }
+    if (b->h_uncertain) (void)hipHostFree(b->h_uncertain);
     (void)hipFree(b->scratch);
     (void)hipFree(b->d_cjobs);
     (void)hipFree(b->d_agg);
@@ -479,6 +481,8 @@ int simsense_batch_create(const simsense_params *params, int32_t n, simsense_bat
             hipEventCreateWithFlags(&b->staged[i], hipEventDisableTiming) != hipSuccess)
             rc = SIMSENSE_ERR_OUT_OF_MEMORY;
     }
+    if (rc == SIMSENSE_OK && hipHostMalloc((void **)&b->h_uncertain, n * sizeof(unsigned), 0) != hipSuccess)
+        rc = SIMSENSE_ERR_OUT_OF_MEMORY;
     if (rc == SIMSENSE_OK && hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking) != hipSuccess)
         rc = SIMSENSE_ERR_DEVICE;
     if (rc == SIMSENSE_OK) rc = build_plan(b);
@@ -569,6 +573,44 @@ int simsense_batch_learned_compute(simsense_batch *b, simsense_net *net, const s
     B_TRY(hipGraphLaunch(b->lexec, st));
     b->last_stream = st;
     net->last_stream = st;
+    return SIMSENSE_OK;
+}
+
+int simsense_batch_learned_fallback(simsense_batch *b, simsense_net *net, simsense_handle *plain,
+                                    const simsense_pair *pairs, float tau, unsigned *uncertain, int32_t mode,
+                                    float max_uncertain_frac, int32_t *fell_back, void *stream)
+{
+    if (!b || !net || !pairs || !uncertain) return SIMSENSE_ERR_NULL_POINTER;
+    if (mode != SIMSENSE_FALLBACK_THRESHOLD && mode != SIMSENSE_FALLBACK_NEVER && mode != SIMSENSE_FALLBACK_ALWAYS)
+        return SIMSENSE_ERR_INVALID_ARGUMENT;
+    if (mode == SIMSENSE_FALLBACK_THRESHOLD && !(max_uncertain_frac >= 0.0f && max_uncertain_frac <= 1.0f))
+        return SIMSENSE_ERR_INVALID_ARGUMENT;
+    if (mode != SIMSENSE_FALLBACK_NEVER) {
+        if (!plain) return SIMSENSE_ERR_NULL_POINTER;
+        // the plain run writes the pair's own outputs, so it must describe the same image
+        for (const Slot &sl : b->slots)
+            if (plain->p.width != sl.p.width || plain->p.height != sl.p.height || plain->p.max_disp != sl.p.max_disp)
+                return SIMSENSE_ERR_INVALID_ARGUMENT;
+    }
+    int rc = simsense_batch_learned_compute(b, net, pairs, tau, uncertain, stream);
+    if (rc != SIMSENSE_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const int n = b->n;
+    if (mode == SIMSENSE_FALLBACK_THRESHOLD) {
+        // the decision needs the counts on the host: one copy and one wait
+        B_TRY(hipMemcpyAsync(b->h_uncertain, uncertain, n * sizeof(unsigned), hipMemcpyDeviceToHost, st));
+        B_TRY(hipStreamSynchronize(st));
+    }
+    const double limit = (double)max_uncertain_frac * (double)b->slots[0].p.width * (double)b->slots[0].p.height;
+    for (int s = 0; s < n; ++s) {
+        const bool fb = mode == SIMSENSE_FALLBACK_ALWAYS ||
+                        (mode == SIMSENSE_FALLBACK_THRESHOLD && (double)b->h_uncertain[s] > limit);
+        if (fell_back) fell_back[s] = fb ? 1 : 0;
+        if (!fb) continue;
+        const simsense_pair &pr = pairs[s];
+        rc = simsense_compute(plain, pr.left, pr.right, pr.pitch, pr.depth, pr.disp, pr.flags, stream);
+        if (rc != SIMSENSE_OK) return rc;
+    }
     return SIMSENSE_OK;
 }
 

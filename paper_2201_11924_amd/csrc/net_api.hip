@@ -150,8 +150,7 @@ int simsense_net_create(int64_t max_pixels, uint64_t seed, simsense_net **out)
     for (int l = 0; l < 3; ++l) sz[k++] = a256(P * 64);  // act
     sz[k++] = a256(P * 8);           // out
     sz[k++] = a256(P * 32);          // dy4
-    sz[k++] = a256(P * 64);          // g0
-    sz[k++] = a256(P * 64);          // g1
+    for (int l = 0; l < 3; ++l) sz[k++] = a256(P * 64);  // g[l]
     sz[k++] = a256((size_t)wblocks * 32 * 9 * 32 * sizeof(float));  // wpart
     sz[k++] = a256((size_t)kBiasBlocks * 32 * sizeof(float));       // bpart
     sz[k++] = a256((size_t)kLossBlocks * 3 * sizeof(float));        // lpart
@@ -177,8 +176,7 @@ int simsense_net_create(int64_t max_pixels, uint64_t seed, simsense_net **out)
     for (int l = 0; l < 3; ++l) n->act[l] = (uint16_t *)take();
     n->out = (float *)take();
     n->dy4 = (uint16_t *)take();
-    n->g[0] = (uint16_t *)take();
-    n->g[1] = (uint16_t *)take();
+    for (int l = 0; l < 3; ++l) n->g[l] = (uint16_t *)take();
     n->wpart = (float *)take();
     n->bpart = (float *)take();
     n->lpart = (float *)take();
@@ -188,6 +186,7 @@ int simsense_net_create(int64_t max_pixels, uint64_t seed, simsense_net **out)
     n->t_valid = (uint8_t *)take();
     n->last_stream = nullptr;
     n->step = 0;
+    n->last_P = 0;
     float *host = new (std::nothrow) float[kNumParams];
     if (!host) { (void)hipFree(n->block); delete n; return SIMSENSE_ERR_OUT_OF_MEMORY; }
     init_params(host, seed);
@@ -262,6 +261,33 @@ int simsense_net_get_grads(simsense_net *n, float *grads, int64_t count)
     return SIMSENSE_OK;
 }
 
+int simsense_net_read_tensor(simsense_net *n, int32_t what, int32_t layer, void *host, int64_t bytes)
+{
+    if (!n || !host) return SIMSENSE_ERR_NULL_POINTER;
+    const int64_t P = n->last_P;
+    const void *src = nullptr;
+    int64_t size = 0;
+    if (what == SIMSENSE_NET_ACTIVATION && layer >= 0 && layer < 3) {
+        src = n->act[layer];
+        size = P * 32 * 2;
+    } else if (what == SIMSENSE_NET_OUTPUT && layer == 3) {
+        src = n->out;
+        size = P * 2 * 4;
+    } else if (what == SIMSENSE_NET_OUTPUT_GRAD && layer >= 0 && layer < 3) {
+        src = n->g[layer];
+        size = P * 32 * 2;
+    } else if (what == SIMSENSE_NET_OUTPUT_GRAD && layer == 3) {
+        src = n->dy4;
+        size = P * 16 * 2;
+    } else {
+        return SIMSENSE_ERR_INVALID_ARGUMENT;
+    }
+    if (P == 0 || bytes != size) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    if (hipStreamSynchronize(n->last_stream) != hipSuccess) return SIMSENSE_ERR_DEVICE;
+    NET_TRY(hipMemcpy(host, src, (size_t)size, hipMemcpyDeviceToHost));
+    return SIMSENSE_OK;
+}
+
 int simsense_net_forward(simsense_net *n, const uint16_t *features, int32_t batch, int32_t height, int32_t width,
                          float *out, void *stream)
 {
@@ -270,6 +296,7 @@ int simsense_net_forward(simsense_net *n, const uint16_t *features, int32_t batc
     if (rc != SIMSENSE_OK) return rc;
     hipStream_t s = (hipStream_t)stream;
     n->last_stream = s;
+    n->last_P = (int64_t)batch * height * width;
     rc = enqueue_forward(n, features, batch, height, width, s);
     if (rc != SIMSENSE_OK) return rc;
     NET_TRY(hipMemcpyAsync(out, n->out, (size_t)batch * height * width * 2 * sizeof(float),
@@ -288,6 +315,7 @@ int simsense_net_train_step(simsense_net *n, const uint16_t *features, const flo
     hipStream_t s = (hipStream_t)stream;
     n->last_stream = s;
     const int64_t P = (int64_t)batch * height * width;
+    n->last_P = P;
     rc = enqueue_forward(n, features, batch, height, width, s);
     if (rc != SIMSENSE_OK) return rc;
 
@@ -301,7 +329,6 @@ int simsense_net_train_step(simsense_net *n, const uint16_t *features, const flo
     // gradient at each layer's output, layer inputs
     const uint16_t *dy = n->dy4;
     const uint16_t *xin[4] = {features, n->act[0], n->act[1], n->act[2]};
-    int gi = 0;
     for (int l = 3; l >= 0; --l) {
         WgradArgs wa{};
         wa.x = xin[l]; wa.dy = dy; wa.partial = n->wpart; wa.bpartial = n->bpart;
@@ -316,19 +343,19 @@ int simsense_net_train_step(simsense_net *n, const uint16_t *features, const flo
         if (l > 0) {
             // gradient at the previous layer's output: backward-data conv, masked by its ReLU
             ConvArgs c{};
-            c.in = dy; c.weights = n->wb[l]; c.bias = nullptr; c.mask = xin[l]; c.out = n->g[gi];
+            c.in = dy; c.weights = n->wb[l]; c.bias = nullptr; c.mask = xin[l]; c.out = n->g[l - 1];
             c.batch = batch; c.H = height; c.W = width;
             NET_TRY(launch_conv(c, kLayers[l].coutp, kLayers[l].cinp, EPI_MASK, s));
-            dy = n->g[gi];
-            gi ^= 1;
+            dy = n->g[l - 1];
         }
     }
     n->step += 1;
     AdamArgs ad{};
     ad.p = n->params; ad.m = n->m; ad.v = n->v; ad.grad = n->grad; ad.n = kNumParams;
     ad.lr = lr; ad.b1 = 0.9f; ad.b2 = 0.999f; ad.eps = 1e-8f;
-    ad.c1 = (float)(1.0 - pow(0.9, (double)n->step));
-    ad.c2 = (float)(1.0 - pow(0.999, (double)n->step));
+    // bias corrections from the same (float32) decay rates the moments use
+    ad.c1 = (float)(1.0 - pow((double)ad.b1, (double)n->step));
+    ad.c2 = (float)(1.0 - pow((double)ad.b2, (double)n->step));
     NET_TRY(launch_adam(ad, s));
     NET_TRY(launch_relayout(relayout_args(n), s));
     if (loss) NET_TRY(hipMemcpyAsync(loss, n->loss, 3 * sizeof(float), hipMemcpyDeviceToDevice, s));

@@ -154,7 +154,8 @@ struct simsense_net {
     uint16_t *act[3];      // [P][32] outputs of layers 1..3
     float *out;            // [P][2]
     uint16_t *dy4;         // [P][16]
-    uint16_t *g[2];        // [P][32] backward ping-pong
+    uint16_t *g[3];        // [P][32] gradient at the output of layer l (ReLU-masked), l = 0..2
+    int64_t last_P;        // pixels of the last forward or training call
     float *wpart, *bpart;  // weight / bias gradient partials
     float *lpart, *scal, *loss;
     float *t_res;          // targets of the learned depth path's own use (training helpers)

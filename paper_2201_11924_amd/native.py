@@ -339,6 +339,8 @@ _lib.simsense_net_train_step.argtypes = [_vp, _vp, _vp, _vp, _i32, _i32, _i32, c
 _lib.simsense_net_targets.argtypes = [_vp, _vp, _vp, _vp, _vp, _i64, _vp]
 _lib.simsense_net_infer.argtypes = [_vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, ct.c_float, _vp, _vp]
 _lib.simsense_learned_compute.argtypes = [_vp, _vp, _vp, _vp, _i32, ct.POINTER(Outputs), _vp]
+_lib.simsense_net_read_tensor.argtypes = [_vp, _i32, _i32, _vp, _i64]
+NET_ACTIVATION, NET_OUTPUT, NET_OUTPUT_GRAD = 0, 1, 2
 
 NUM_NET_PARAMS = int(_lib.simsense_net_num_params())
 
@@ -390,6 +392,19 @@ class Net:
         g = np.empty(NUM_NET_PARAMS, np.float32)
         _check(_lib.simsense_net_get_grads(self._h, g.ctypes.data_as(_fp), NUM_NET_PARAMS), "simsense_net_get_grads")
         return g
+
+    def read_tensor(self, what: int, layer: int, pixels: int):
+        """A tensor the last forward / training call left in the net, as a numpy
+        array: bf16 bits (uint16) [pixels, C] for activations and gradients, fp32
+        [pixels, 2] for the output."""
+        import numpy as np
+        if what == NET_OUTPUT:
+            a = np.empty((pixels, 2), np.float32)
+        else:
+            a = np.empty((pixels, 16 if (what == NET_OUTPUT_GRAD and layer == 3) else 32), np.uint16)
+        _check(_lib.simsense_net_read_tensor(self._h, what, layer, a.ctypes.data_as(_vp), a.nbytes),
+               "simsense_net_read_tensor")
+        return a
 
     def forward(self, features: torch.Tensor, stream=None) -> torch.Tensor:
         B, H, W, C = features.shape
@@ -481,6 +496,9 @@ _lib.simsense_batch_compute.argtypes = [_vp, ct.POINTER(Pair), _vp]
 _lib.simsense_batch_set_tuning.argtypes = [_vp, ct.POINTER(Tuning)]
 _lib.simsense_batch_get_tuning.argtypes = [_vp, ct.POINTER(Tuning)]
 _lib.simsense_batch_learned_compute.argtypes = [_vp, _vp, ct.POINTER(Pair), ct.c_float, _vp, _vp]
+_lib.simsense_batch_learned_fallback.argtypes = [_vp, _vp, _vp, ct.POINTER(Pair), ct.c_float, _vp, _i32,
+                                                 ct.c_float, ct.POINTER(_i32), _vp]
+FALLBACK_THRESHOLD, FALLBACK_NEVER, FALLBACK_ALWAYS = 0, 1, 2
 _lib.simsense_batch_autotune.argtypes = [_vp, ct.POINTER(Pair), _i32, ct.POINTER(Tuning), ct.POINTER(ct.c_float),
                                          _i32, ct.POINTER(_i32), _vp]
 
@@ -542,6 +560,21 @@ class Batch:
             raise ValueError("uncertain: int32 GPU tensor with one entry per pair")
         _check(_lib.simsense_batch_learned_compute(self._h, net._h, arr, float(tau), _ptr(uncertain),
                                                    _stream(stream)), "simsense_batch_learned_compute")
+
+    def learned_fallback(self, net: "Net", plain: Optional["SimSense"], lefts, rights, outs, tau: float,
+                         uncertain: torch.Tensor, mode: int = FALLBACK_THRESHOLD, max_uncertain_frac: float = 0.25,
+                         stream=None):
+        """The learned form, then plain SGM (the `plain` handle) for the pairs that fall
+        back, over their own outputs; returns the per-pair fallback decisions (list of 0/1)."""
+        arr = self._pairs(lefts, rights, outs)
+        if uncertain.dtype != torch.int32 or uncertain.numel() != len(self.params) or not uncertain.is_cuda:
+            raise ValueError("uncertain: int32 GPU tensor with one entry per pair")
+        fb = (_i32 * len(self.params))()
+        _check(_lib.simsense_batch_learned_fallback(self._h, net._h, plain._h if plain is not None else None, arr,
+                                                    float(tau), _ptr(uncertain), int(mode),
+                                                    float(max_uncertain_frac), fb, _stream(stream)),
+               "simsense_batch_learned_fallback")
+        return list(fb)
 
     def set_tuning(self, horizontal_lanes: int = 0, blocks_per_cu: int = 2):
         t = Tuning(ct.sizeof(Tuning), horizontal_lanes, blocks_per_cu)

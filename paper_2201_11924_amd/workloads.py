@@ -11,6 +11,8 @@ Workloads:
   batch         `--pairs` copies of one 1280x720 pair as plain 8-path and as the
                 learned 2-path+net form, one graph launch each per repetition
   net           fused inference of the learned net on `--pairs` 1280x720 feature maps
+  train         `--reps` training steps of the learned net on a batch of `--pairs`
+                640x480 feature maps (the training workload's batch shape)
 """
 from __future__ import annotations
 
@@ -99,16 +101,36 @@ def run_net(nat, torch, args):
     return f"net images={B} reps={args.reps}"
 
 
+def run_train(nat, torch, args):
+    B, H, W = args.pairs, 480, 640
+    rng = np.random.default_rng(1)
+    x = np.zeros((B, H, W, 8), np.float32)
+    x[..., :4] = rng.uniform(0, 1, (B, H, W, 4)).astype(np.float32)
+    f = torch.from_numpy((x.view(np.uint32) >> 16).astype(np.uint16)).cuda().view(torch.int16)
+    t = torch.from_numpy(rng.uniform(-1.5, 1.5, (B, H, W)).astype(np.float32)).cuda()
+    v = torch.from_numpy((rng.random((B, H, W)) < 0.85).astype(np.uint8)).cuda()
+    net = nat.Net(B * H * W, seed=1)
+    net.train_step(f, t, v, 1e-3)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.reps):
+        net.train_step(f, t, v, 1e-3)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / args.reps * 1000
+    net.close()
+    return f"train batch={B} {W}x{H} steps={args.reps}: {ms:.3f} ms/step"
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("workload", choices=("pair", "batch", "net"))
+    ap.add_argument("workload", choices=("pair", "batch", "net", "train"))
     ap.add_argument("--paths", type=int, default=8)
     ap.add_argument("--pairs", type=int, default=64)
     ap.add_argument("--reps", type=int, default=4)
     args = ap.parse_args(argv)
     import torch
     import paper_2201_11924_amd.native as nat
-    fn = {"pair": run_pair, "batch": run_batch, "net": run_net}[args.workload]
+    fn = {"pair": run_pair, "batch": run_batch, "net": run_net, "train": run_train}[args.workload]
     print(fn(nat, torch, args), flush=True)
 
 

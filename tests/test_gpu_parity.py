@@ -233,3 +233,14 @@ def test_sgbm_parameter_bounds(nat):
             nat.SimSense(dict(p, **bad))
     with pytest.raises(nat.SimSenseError):
         nat.Batch([p])
+
+
+def test_sgbm_paper_shape_matches_oracle(orc, nat):
+    """Block matching at the paper's Table II shape (960x540, 4 paths, D = 128,
+    3x3 blocks with P1/P2 scaled by the block area, as the benchmark runs it)."""
+    cfg = sensor_like(960, 540, 128)
+    params = dict(cfg["params"], num_paths=4, block_w=3, block_h=3, p1=7 * 9, p2=86 * 9)
+    pr = make_pair(cfg["spec"], 424242)
+    left = orc.ir_noise(pr.left, pr.gamma_l, pr.n_l)
+    right = orc.ir_noise(pr.right, pr.gamma_r, pr.n_r)
+    compare(orc, nat, params, left, right, label="sgbm 960x540")

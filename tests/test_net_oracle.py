@@ -55,6 +55,29 @@ def test_adam_first_step_is_signed_lr():
     assert np.allclose(p, [1.0 - 0.01, -2.0 + 0.01, 3.0 - 0.01], atol=1e-9)
 
 
+def test_adam_three_steps_hand_computed():
+    """Steps 1-3 of one parameter (p0 = 0.5, lr = 0.1, gradients 1, -2, 0.5), worked
+    out by hand from the update of Kingma and Ba (Algorithm 1): m_t = b1 m + (1-b1) g,
+    v_t = b2 v + (1-b2) g^2, p -= lr (m_t / (1-b1^t)) / (sqrt(v_t / (1-b2^t)) + eps).
+    From step 2 on the two decay rates no longer cancel, so swapping them fails."""
+    p, m, v = np.array([0.5]), np.zeros(1), np.zeros(1)
+    want = [  # (m, v, p) after each step
+        (0.1, 0.001, 0.400000001),
+        (-0.11, 0.004999, 0.43661035347207509),   # m^ = -0.11/0.19, v^ = 0.004999/0.001999
+        (-0.049, 0.005244001, 0.45027941967382173),  # m^ = -0.049/0.271, v^ = 0.005244001/0.002997001
+    ]
+    for t, (g, (wm, wv, wp)) in enumerate(zip((1.0, -2.0, 0.5), want), 1):
+        no.adam_step(p, np.array([g]), m, v, t, 0.1)
+        assert m[0] == pytest.approx(wm, rel=1e-12)
+        assert v[0] == pytest.approx(wv, rel=1e-12)
+        assert p[0] == pytest.approx(wp, rel=1e-12)
+    # the swapped decay rates give another parameter at step 2
+    p2, m2, v2 = np.array([0.5]), np.zeros(1), np.zeros(1)
+    for t, g in enumerate((1.0, -2.0), 1):
+        no.adam_step(p2, np.array([g]), m2, v2, t, 0.1, b1=0.999, b2=0.9)
+    assert abs(p2[0] - 0.43661035347207509) > 1e-3
+
+
 def test_bf16_rounding_known_values():
     vals = np.array([1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, -3.0, 1e-3, 65504.0], np.float32)
     got = no.bf16_round(vals)
