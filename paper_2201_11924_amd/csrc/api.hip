@@ -8,6 +8,7 @@
 
 #include "internal.h"
 #include "net_internal.h"
+#include "trace.h"
 
 namespace ss {
 
@@ -40,9 +41,11 @@ int validate(const simsense_params *p)
     if (p->census_w < 1 || p->census_h < 1 || !(p->census_w & 1) || !(p->census_h & 1))
         return SIMSENSE_ERR_INVALID_ARGUMENT;
     if (p->census_mode != 0 && p->census_mode != 1) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    // (the sides are bounded before they are multiplied)
+    if (p->census_w > 65 || p->census_h > 65) return SIMSENSE_ERR_INVALID_ARGUMENT;
     if (p->census_w * p->census_h < 3) return SIMSENSE_ERR_INVALID_ARGUMENT;
     const int bits = census_bits(p->census_w, p->census_h, p->census_mode);
-    if (bits > 64 || p->census_w > 65 || p->census_h > 65) return SIMSENSE_ERR_INVALID_ARGUMENT;
+    if (bits > 64) return SIMSENSE_ERR_INVALID_ARGUMENT;
     if (p->block_w < 1 || p->block_h < 1 || p->block_w > 2 * kMaxBlockHalf + 1 || p->block_h > 2 * kMaxBlockHalf + 1 || !(p->block_w & 1) ||
         !(p->block_h & 1))
         return SIMSENSE_ERR_INVALID_ARGUMENT;
@@ -300,6 +303,7 @@ int enqueue_match(simsense_handle *h, const uint8_t *left, const uint8_t *right,
     const simsense_params &p = h->p;
     const int W = p.width, H = p.height, D = p.max_disp;
     h->last_stream = s;
+    TraceRange range("simsense match");
     profile_mark(h, SIMSENSE_PASS_CENSUS, false, s);
     const bool queue = !h->sgbm && h->tuning.blocks_per_cu > 0;
     SS_TRY(launch_census(left, pitch, W, H, p.census_w, p.census_h, p.census_mode, h->census_l, h->wide, s));
@@ -379,6 +383,7 @@ int enqueue_post(simsense_handle *h, const float *masked, const uint8_t *flags_p
     pa.W = p.width; pa.H = p.height; pa.median = p.median;
     pa.fb = p.focal_px * p.baseline_m;
     pa.disp = o->disp; pa.depth = o->depth; pa.flags = o->flags;
+    TraceRange range("simsense post");
     profile_mark(h, SIMSENSE_PASS_POST, false, s);
     if (pa.disp || pa.depth || pa.flags) SS_TRY(launch_post(pa, s));
     profile_mark(h, SIMSENSE_PASS_POST, true, s);
@@ -475,6 +480,7 @@ int simsense_compute_ex(simsense_handle *h, const uint8_t *left, const uint8_t *
     hipStream_t s = (hipStream_t)stream;
     const int W = p.width, H = p.height, D = p.max_disp;
     const size_t npx = (size_t)W * H;
+    TraceRange range("simsense_compute");
     int rc = profile_begin_call(h);
     if (rc != SIMSENSE_OK) return rc;
     rc = enqueue_match(h, left, right, pitch, s, o->volume);

@@ -16,6 +16,7 @@
 
 #include "internal.h"
 #include "net_internal.h"
+#include "trace.h"
 
 using namespace ss;
 
@@ -532,6 +533,7 @@ int simsense_batch_compute(simsense_batch *b, const simsense_pair *pairs, void *
     if (!b || !pairs) return SIMSENSE_ERR_NULL_POINTER;
     int rc = check_pairs(b, pairs);
     if (rc != SIMSENSE_OK) return rc;
+    TraceRange range("simsense_batch_compute");
     hipStream_t st = (hipStream_t)stream;
     if (!b->captured) {
         rc = capture(b);
@@ -555,6 +557,7 @@ int simsense_batch_learned_compute(simsense_batch *b, simsense_net *net, const s
     if ((int64_t)b->slots[0].p.width * b->slots[0].p.height > net->max_pixels) return SIMSENSE_ERR_INVALID_ARGUMENT;
     int rc = check_pairs(b, pairs);
     if (rc != SIMSENSE_OK) return rc;
+    TraceRange range("simsense_batch_learned_compute");
     hipStream_t st = (hipStream_t)stream;
     if (b->lcaptured && (b->lnet != net || b->ltau != tau || b->luncertain != uncertain)) {
         (void)hipGraphExecDestroy(b->lexec);
@@ -592,6 +595,7 @@ int simsense_batch_learned_fallback(simsense_batch *b, simsense_net *net, simsen
             if (plain->p.width != sl.p.width || plain->p.height != sl.p.height || plain->p.max_disp != sl.p.max_disp)
                 return SIMSENSE_ERR_INVALID_ARGUMENT;
     }
+    TraceRange range("simsense_batch_learned_fallback");
     int rc = simsense_batch_learned_compute(b, net, pairs, tau, uncertain, stream);
     if (rc != SIMSENSE_OK) return rc;
     hipStream_t st = (hipStream_t)stream;

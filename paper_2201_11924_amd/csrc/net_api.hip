@@ -7,6 +7,7 @@
 
 #include "internal.h"
 #include "net_internal.h"
+#include "trace.h"
 
 namespace ss {
 namespace net {
@@ -314,6 +315,7 @@ int simsense_net_train_step(simsense_net *n, const uint16_t *features, const flo
     if (!(lr >= 0.0f) || !isfinite(lr)) return SIMSENSE_ERR_INVALID_ARGUMENT;
     hipStream_t s = (hipStream_t)stream;
     n->last_stream = s;
+    TraceRange range("simsense_net_train_step");
     const int64_t P = (int64_t)batch * height * width;
     n->last_P = P;
     rc = enqueue_forward(n, features, batch, height, width, s);
@@ -400,6 +402,7 @@ int simsense_learned_compute(simsense_handle *h, simsense_net *n, const uint8_t 
     if (p.block_w * p.block_h > 1) return SIMSENSE_ERR_UNSUPPORTED;  // the net was trained on SGM costs
     hipStream_t s = (hipStream_t)stream;
     n->last_stream = s;
+    TraceRange range("simsense_learned_compute");
     const int64_t P = (int64_t)p.width * p.height;
     int rc = profile_begin_call(h);
     if (rc != SIMSENSE_OK) return rc;
