@@ -36,6 +36,10 @@ __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi)
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
+// ReLU on the bit pattern: negative values (sign bit set) become +0, the rest
+// pass unchanged; one integer max, with none of the quieting a float max needs
+__device__ __forceinline__ float relu(float v) { return __int_as_float(max(__float_as_int(v), 0)); }
+
 __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v)
 {
     bf16x8 r;
@@ -82,9 +86,13 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a)
             y = r / a.W;
             x = r - y * a.W;
         }
+        // the bias is the accumulators' starting value (forward epilogues), so
+        // the products are summed onto it in k order
         floatx4 acc[MB];
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) acc[mb] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int mb = 0; mb < MB; ++mb)
+            acc[mb] = EPI == EPI_MASK ? floatx4{0.f, 0.f, 0.f, 0.f}
+                                      : floatx4{bias[mb][0], bias[mb][1], bias[mb][2], bias[mb][3]};
 #pragma unroll
         for (int c = 0; c < NK; ++c) {
             // B fragment: k = 32*c + 8*quad .. +7 of pixel p
@@ -109,8 +117,8 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a)
             if (EPI == EPI_LINEAR) {
                 if (co == 0) {
                     float *o = (float *)a.out + p * 2;
-                    o[0] = acc[mb][0] + bias[mb][0];
-                    o[1] = acc[mb][1] + bias[mb][1];
+                    o[0] = acc[mb][0];
+                    o[1] = acc[mb][1];
                 }
             } else {
                 float h[4];
@@ -118,7 +126,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a)
                 for (int i = 0; i < 4; ++i) {
                     float v = acc[mb][i];
                     if (EPI == EPI_RELU) {
-                        v = fmaxf(v + bias[mb][i], 0.0f);
+                        v = relu(v);
                     } else {
                         const uint16_t mk = a.mask[p * COUTP + co + i];
                         v = (mk & 0x7FFF) != 0 && !(mk & 0x8000) ? v : 0.0f;  // mask > 0

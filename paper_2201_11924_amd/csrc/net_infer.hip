@@ -2,12 +2,28 @@
 // net and the combination with the 2-path disparity in one kernel, with no
 // activation ever leaving the chip.
 //
-// A block owns a strip of kOutW output columns and a segment of rows of one
-// image and slides down it one row per step.  Each layer keeps the last three
-// rows of its output for the strip (plus a 4-column halo on each side) in an
-// LDS ring, so a step computes exactly one new row of every layer:
-//   feature row r  ->  layer-1 row r-1  ->  layer-2 row r-2  ->  layer-3 row r-3
-//   ->  layer-4 row r-4 (residual and logit) -> combination -> HBM.
+// A block (4 waves) owns a strip of kOutW output columns and a segment of rows
+// of one image and slides down it one row per step.  Every layer is computed
+// over the same kRingW = 128 columns (the strip plus a 4-column halo each side)
+// and keeps its recent output rows in an LDS ring of 4 slots.  The layers run
+// skewed by two rows, so that at step s
+//   feature row s+1 is stored, layer 1 computes row s-1, layer 2 row s-3,
+//   layer 3 row s-5 and layer 4 row s-7 (residual and logit -> combination),
+// each from input rows that were complete before the step began: a step needs
+// one barrier, at its start.
+//
+// Each wave owns two 16-column MFMA tiles of every layer row and keeps every
+// weight of the net as MFMA A fragments in registers.  A 3x3 layer's output row
+// j reads input rows j-1, j and j+1, and row j+1's output reads j, j+1, j+2, so
+// for layers 2 and 3 a wave keeps the B fragments of the last three input rows
+// of its tiles in registers (a 3-row register ring, phase fixed at compile time
+// by unrolling the step loop three times) and reads only the newest input row
+// from LDS.  Layer 1 (4 input channels, 4 taps per k step) and layer 4 read
+// their B fragments from the rings.  In LDS a pixel's 32 channels are four
+// 16-byte chunks; chunk c of ring pixel p sits at position c ^ ((p >> 1) & 3),
+// so the 16-byte fragment reads of 8 consecutive pixels hit 8 different 4-bank
+// groups.
+//
 // Rows and columns outside the image are stored as zeros in every ring (the
 // zero padding of the next layer), so each layer sees exactly the input the
 // per-layer kernels see.  The GEMM shapes, operand layouts, k order and
@@ -26,14 +42,19 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-constexpr int kTiles = 6;                       // 16-column MFMA tiles per ring row
-constexpr int kRingW = 16 * kTiles;             // computed columns per layer row
-constexpr int kHalo = 4;                        // one column per remaining layer
-constexpr int kOutW = kRingW - 2 * kHalo - 8;   // output columns per strip (5 tiles)
-constexpr int kRowPx = kRingW + 2;              // + one zero column on each side
-constexpr int kOutTiles = kOutW / 16;
-static_assert(kOutW % 16 == 0, "output strip must be whole tiles");
-static_assert(kHalo + kOutW + kHalo <= kRingW, "ring too narrow for the halo");
+constexpr int kWaves = 4;
+constexpr int kTiles = 2 * kWaves;               // 16-column MFMA tiles per layer row, two per wave
+constexpr int kRingW = 16 * kTiles;              // computed columns per layer row
+constexpr int kHalo = 4;                         // one column per layer on each side
+constexpr int kOutW = kRingW - 2 * kHalo;        // output columns per strip
+// ring pixels: a zero column, the computed columns, and a zero tail that the
+// last layer-4 tile reads (it starts kHalo columns in and reaches one column past)
+constexpr int kRowPx = 1 + kRingW + kHalo + 1;
+constexpr int kSlots = 4;                        // rows per ring
+constexpr int kSkew = 2;                         // rows between consecutive layers
+constexpr int kLead = 1;                         // the feature row stored at step s is s + kLead
+// (the last layer-4 tile reads ring columns up to kHalo + kRingW, pixel index one more)
+static_assert(kHalo + kRingW + 1 < kRowPx, "layer-4 tiles must stay inside the ring row");
 
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 // two values as one packed word, the first in the low half (v_cvt_pk_bf16_f32)
@@ -43,6 +64,10 @@ __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi)
     return __builtin_bit_cast(uint32_t, v);
 }
 
+// ReLU on the bit pattern: negative values (sign bit set) become +0, the rest
+// pass unchanged; one integer max, with none of the quieting a float max needs
+__device__ __forceinline__ float relu(float v) { return __int_as_float(max(__float_as_int(v), 0)); }
+
 __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v)
 {
     bf16x8 r;
@@ -50,114 +75,41 @@ __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v)
     return r;
 }
 
-// Layers 2 and 3 keep their weights in registers; layers 1 and 4 read theirs
-// from LDS (rows padded by 16 bytes so a fragment read spreads over the banks).
-constexpr int kW1Row = kpad(8) / 8 + 1, kW4Row = kpad(32) / 8 + 1;  // uint4 per padded row
-
 struct Smem {
-    uint4 feat[3][kRowPx];          // 8 bf16 feature channels per pixel
-    uint4 act[3][3][kRowPx][4];     // [layer][ring slot][pixel][32 bf16 channels, chunks swizzled]
-    uint4 w1[32][kW1Row];
-    uint4 w4[16][kW4Row];
-    float4 bias[3][8];              // layers 1..3, 32 channels each
-    float b4[2];                    // layer 4, channels 0 and 1
-    unsigned count[4];
+    uint4 feat[kSlots][kRowPx];          // 8 bf16 feature channels per pixel
+    uint4 act[3][kSlots][kRowPx][4];     // [layer][slot][pixel][32 bf16 channels, chunks swizzled]
+    float4 bias[3][8];                   // layers 1..3, 32 channels each
+    float b4[2];                         // layer 4, channels 0 and 1
+    unsigned count[kWaves];
 };
 
-__device__ __forceinline__ int slot_of(int j) { return (j + 6) % 3; }  // rows j >= -6
+// ring slot of image row r (rows down to -16)
+__device__ __forceinline__ int slot4(int r) { return (r + 16) & (kSlots - 1); }
+__device__ __forceinline__ int swz(int p, int c) { return c ^ ((p >> 1) & 3); }
 
-// A pixel's 32 channels are four 16-byte chunks; chunk c of ring pixel p is
-// stored at position c ^ ((p >> 2) & 3), so that the 16 lanes reading one
-// chunk of 16 consecutive pixels (64 bytes apart) hit 16 different 4-bank groups.
-__device__ __forceinline__ int swz(int p, int c) { return c ^ ((p >> 2) & 3); }
-
-// One 32-channel ReLU layer row: 6 tiles x 2 output-channel blocks = 12 units,
-// three per wave (units 3w .. 3w+2, unit u = tile u/2, channel block u%2); a
-// wave's units touch two tiles, whose B fragments it loads once per k step.
-// PAR = wave & 1 fixes which channel block and tile each unit uses, so that all
-// register arrays are indexed by constants.  B fragments are loaded two k
-// steps ahead of the products that use them.
-template <int NK, bool FIRST, int PAR>
-__device__ __forceinline__ void layer_row(Smem &sm, const bf16x8 (&wa)[2][9], int in_layer, int out_layer, int j,
-                                          int xb, int W, int wave, int quad, int col)
+__device__ __forceinline__ bf16x8 act_frag(const Smem &sm, int layer, int slot, int p, int quad)
 {
-    const int u0 = 3 * wave;
-    const int ta = u0 / 2, tb = (u0 + 2) / 2;
-    constexpr int kMb[3] = {PAR, 1 - PAR, PAR};
-    constexpr bool kUseB[3] = {false, PAR == 1, true};
-
-    // B fragment of k step c for tiles ta (va) and tb (vb)
-    auto load_b = [&](int c, uint4 &va, uint4 &vb) {
-        if (FIRST) {
-            // k = 32c + 8 quad .. +7 -> tap 4c + quad (zero beyond the 9 taps), 8 channels
-            const int tap = 4 * c + quad, tc = tap < 9 ? tap : 8;
-            const int slot = slot_of(j - 1 + tc / 3), dx = tc % 3 - 1;
-            va = sm.feat[slot][16 * ta + col + dx + 1];
-            vb = sm.feat[slot][16 * tb + col + dx + 1];
-            if (tap >= 9) va = vb = make_uint4(0, 0, 0, 0);
-        } else {
-            // k = 32c + 8 quad .. +7 -> tap c, channels 8 quad .. +7
-            const int slot = slot_of(j - 1 + c / 3), dx = c % 3 - 1;
-            const int pa = 16 * ta + col + dx + 1, pb = 16 * tb + col + dx + 1;
-            va = sm.act[in_layer][slot][pa][swz(pa, quad)];
-            vb = sm.act[in_layer][slot][pb][swz(pb, quad)];
-        }
-    };
-    floatx4 acc[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) acc[i] = floatx4{0.f, 0.f, 0.f, 0.f};
-    // B fragments two k steps ahead of the products, in a ring of three
-    uint4 bufa[3], bufb[3];
-    load_b(0, bufa[0], bufb[0]);
-    if (NK > 1) load_b(1, bufa[1], bufb[1]);
-#pragma unroll
-    for (int c = 0; c < NK; ++c) {
-        if (c + 2 < NK) load_b(c + 2, bufa[(c + 2) % 3], bufb[(c + 2) % 3]);
-        const bf16x8 ba = as_bf16x8(bufa[c % 3]), bb = as_bf16x8(bufb[c % 3]);
-        bf16x8 a0, a1;
-        if (FIRST) {
-            a0 = as_bf16x8(sm.w1[col][4 * c + quad]);
-            a1 = as_bf16x8(sm.w1[16 + col][4 * c + quad]);
-        } else {
-            a0 = wa[0][c];
-            a1 = wa[1][c];
-        }
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-            acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kMb[i] ? a1 : a0, kUseB[i] ? bb : ba, acc[i], 0, 0, 0);
-    }
-    const int slot = slot_of(j);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        const int mb = kMb[i], t = kUseB[i] ? tb : ta;
-        const int q = 16 * t + col, x = xb + q;
-        const bool inside = x >= 0 && x < W;
-        const float4 bv = sm.bias[out_layer][4 * mb + quad];  // channels 16 mb + 4 quad .. +3
-        const float bias[4] = {bv.x, bv.y, bv.z, bv.w};
-        float v[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) v[e] = inside ? fmaxf(acc[i][e] + bias[e], 0.0f) : 0.0f;
-        uint2 w;
-        w.x = pack_bf16(v[0], v[1]);
-        w.y = pack_bf16(v[2], v[3]);
-        // channels 16 mb + 4 quad .. +3: chunk 2 mb + quad / 2, half quad % 2
-        uint2 *dst = (uint2 *)&sm.act[out_layer][slot][q + 1][0] + 2 * swz(q + 1, 2 * mb + quad / 2) + (quad & 1);
-        *dst = w;
-    }
+    return as_bf16x8(sm.act[layer][slot][p][swz(p, quad)]);
 }
 
-template <int NK, bool FIRST>
-__device__ __forceinline__ void layer_row_any(Smem &sm, const bf16x8 (&wa)[2][9], int in_layer, int out_layer, int j,
-                                              int xb, int W, int wave, int quad, int col)
+// Epilogue of a 32-channel ReLU layer (the bias is the accumulator's starting
+// value): channels 16 mb + 4 quad .. +3 of ring pixel p (chunk 2 mb + quad / 2,
+// half quad % 2), zero outside the image.
+__device__ __forceinline__ void store_relu(Smem &sm, int layer, int slot, int p, int mb, int quad, bool inside,
+                                           const floatx4 &acc)
 {
-    if (wave & 1) layer_row<NK, FIRST, 1>(sm, wa, in_layer, out_layer, j, xb, W, wave, quad, col);
-    else layer_row<NK, FIRST, 0>(sm, wa, in_layer, out_layer, j, xb, W, wave, quad, col);
+    uint2 w;
+    w.x = inside ? pack_bf16(relu(acc[0]), relu(acc[1])) : 0u;
+    w.y = inside ? pack_bf16(relu(acc[2]), relu(acc[3])) : 0u;
+    uint2 *dst = (uint2 *)&sm.act[layer][slot][p][0] + 2 * swz(p, 2 * mb + quad / 2) + (quad & 1);
+    *dst = w;
 }
 
-__device__ __forceinline__ void zero_row(Smem &sm, int layer, int j)
+// starting value of an accumulator: the layer's biases of channels 16 mb + 4 quad .. +3
+__device__ __forceinline__ floatx4 bias_acc(const Smem &sm, int layer, int mb, int quad)
 {
-    const int slot = slot_of(j);
-    for (int i = threadIdx.x; i < kRingW * 4; i += 256) sm.act[layer][slot][1 + i / 4][i % 4] = make_uint4(0, 0, 0, 0);
+    const float4 bv = sm.bias[layer][4 * mb + quad];
+    return floatx4{bv.x, bv.y, bv.z, bv.w};
 }
 
 }  // namespace
@@ -177,7 +129,7 @@ __device__ __forceinline__ uint4 feature_of(const RawFeat &v, float smax, int ma
 }
 
 template <bool FROM_SEL>
-__global__ __launch_bounds__(256, 2) void net_infer_kernel(InferArgs a)
+__global__ __launch_bounds__(256, 1) void net_infer_kernel(InferArgs a)
 {
     __shared__ Smem sm;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -204,22 +156,31 @@ __global__ __launch_bounds__(256, 2) void net_infer_kernel(InferArgs a)
     const uint16_t *s2i = (const uint16_t *)((const uint8_t *)a.s2 + soff);
     const uint8_t *di = a.dint + soff;
 
-    // weights as A fragments: lane holds co = 16 mb + col, k = 32 c + 8 quad .. +7
-    bf16x8 w2[2][9], w3[2][9];
-    for (int i = threadIdx.x; i < 32 * (kpad(8) / 8); i += 256)
-        sm.w1[i / (kpad(8) / 8)][i % (kpad(8) / 8)] = ((const uint4 *)a.w[0])[i];
-    for (int i = threadIdx.x; i < 16 * (kpad(32) / 8); i += 256)
-        sm.w4[i / (kpad(32) / 8)][i % (kpad(32) / 8)] = ((const uint4 *)a.w[3])[i];
-    if (threadIdx.x < 96) (&sm.bias[0][0].x)[threadIdx.x] = a.b[threadIdx.x / 32][threadIdx.x % 32];
-    if (threadIdx.x < 2) sm.b4[threadIdx.x] = a.b[3][threadIdx.x];
+    // every weight of the net as A fragments: lane holds co = 16 mb + col,
+    // k = 32 c + 8 quad .. +7 of the layer's [COUTP][kpad(CINP)] layout
+    bf16x8 w1[2][3], w2[2][9], w3[2][9], w4[3];
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            w1[mb][c] = as_bf16x8(*(const uint4 *)(a.w[0] + (16 * mb + col) * kpad(8) + 32 * c + 8 * quad));
 #pragma unroll
         for (int c = 0; c < 9; ++c) {
             w2[mb][c] = as_bf16x8(*(const uint4 *)(a.w[1] + (16 * mb + col) * kpad(32) + 32 * c + 8 * quad));
             w3[mb][c] = as_bf16x8(*(const uint4 *)(a.w[2] + (16 * mb + col) * kpad(32) + 32 * c + 8 * quad));
         }
     }
+    // layer 4 as a 16-row product over one input row: row m = 2 ky + c (c the
+    // output channel, ky the kernel row; rows 6..15 zero), k = 32 kx + ci, so
+    // each new layer-3 row feeds the three output rows it reaches
+#pragma unroll
+    for (int kx = 0; kx < 3; ++kx) {
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (col < 6) v = *(const uint4 *)(a.w[3] + (col % 2) * kpad(32) + 32 * (3 * (col / 2) + kx) + 8 * quad);
+        w4[kx] = as_bf16x8(v);
+    }
+    if (threadIdx.x < 96) (&sm.bias[0][0].x)[threadIdx.x] = a.b[threadIdx.x / 32][threadIdx.x % 32];
+    if (threadIdx.x < 2) sm.b4[threadIdx.x] = a.b[3][threadIdx.x];
 
     // Wait for the weight loads here, once: otherwise the waits the compiler
     // places before their first use inside the loop would, on every step, also
@@ -227,20 +188,19 @@ __global__ __launch_bounds__(256, 2) void net_infer_kernel(InferArgs a)
     // other counters at their maximum.)
     __builtin_amdgcn_s_waitcnt((0x7 << 4) | (0xF << 8));
 
-    // zero every ring (the side columns stay zero for good)
-    for (int i = threadIdx.x; i < 3 * kRowPx; i += 256) (&sm.feat[0][0])[i] = make_uint4(0, 0, 0, 0);
-    for (int i = threadIdx.x; i < 3 * 3 * kRowPx * 4; i += 256) (&sm.act[0][0][0][0])[i] = make_uint4(0, 0, 0, 0);
+    // zero every ring (the zero columns stay zero for good)
+    for (int i = threadIdx.x; i < kSlots * kRowPx; i += 256) (&sm.feat[0][0])[i] = make_uint4(0, 0, 0, 0);
+    for (int i = threadIdx.x; i < 3 * kSlots * kRowPx * 4; i += 256) (&sm.act[0][0][0][0])[i] = make_uint4(0, 0, 0, 0);
 
-    // Every global load of a step is issued at its start (the next feature row,
-    // this step's 2-path disparities) together with the stores of the previous
-    // step's outputs, and nothing waits on them until the layers have run, so
-    // memory latency hides behind the step's matrix work.  Loads use clamped
-    // addresses and are issued unconditionally; out-of-image values are zeroed
-    // where they are consumed.
+    // The global loads of a step (the feature row stored next step, the 2-path
+    // disparities of this step's layer-4 row) are issued at its start together
+    // with the stores of the previous step's outputs, and nothing waits on them
+    // until the layers have run.  Loads use clamped addresses and are issued
+    // unconditionally; out-of-image values are zeroed where they are consumed.
     //
-    // feature row prefetch: thread q < 128 holds pixel xb + q of the row
-    const int fq = threadIdx.x & 127, fx = min(max(xb + fq, 0), W - 1);
-    const bool fq_inside = fq < kRingW && xb + fq >= 0 && xb + fq < W;
+    // feature rows: thread q < kRingW holds pixel xb + q of the row
+    const int fq = threadIdx.x & (kRingW - 1), fx = min(max(xb + fq, 0), W - 1);
+    const bool fq_inside = xb + fq >= 0 && xb + fq < W;
     auto fetch = [&](int r) { return feat[(int64_t)min(max(r, 0), H - 1) * W + fx]; };
     // (from the selection outputs: the raw values are loaded here and turned into
     // features when they are stored, a step later, so no load is waited on early)
@@ -253,117 +213,235 @@ __global__ __launch_bounds__(256, 2) void net_infer_kernel(InferArgs a)
         v.d = di[p];
         return v;
     };
+
+    // step range: layer 4 (row s - 7) covers rows y0 .. y1-1, so the features
+    // (row s + 1) run from y0 - 4 to y1 + 3
+    constexpr int D1 = 1, D2 = D1 + kSkew, D3 = D2 + kSkew, D4 = D3 + kSkew;  // row lag of layers 1..4
+    const int s0 = y0 - 4 - kLead, s_end = y1 - 1 + D4;
+    const int nsteps = s_end - s0 + 1;
+
     uint4 next = make_uint4(0, 0, 0, 0);
     RawFeat next_raw{0u, 0u, 0u, 0u};
-    if (threadIdx.x < 128) {
-        if constexpr (FROM_SEL) next_raw = fetch_raw(y0 - 4);
-        else next = fetch(y0 - 4);
+    if (threadIdx.x < kRingW) {
+        if constexpr (FROM_SEL) next_raw = fetch_raw(s0 + kLead);
+        else next = fetch(s0 + kLead);
     }
     unsigned unsure = 0;
-    // layer-4 results of the previous step: row prow (-1: none), tiles wave and wave + 4
+    // layer-4 results of the previous step: row prow (-1: none), this wave's tiles,
+    // and the 2-path disparities of that row (loaded during that step)
     float pres[2] = {0.0f, 0.0f}, pz[2] = {0.0f, 0.0f}, pd2[2] = {0.0f, 0.0f};
     int prow = -1;
+    const int t_first = 2 * wave;
     auto flush = [&]() {
-        if (prow < 0 || quad != 0) return;
+        if (prow < 0 || quad != 1) return;
+        // every value first (the disparities were loaded a step ago), then the
+        // stores, so that no wait lands between the stores
+        float dv[2];
+        uint8_t fv[2];
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
-            const int t = wave + 4 * k, x = x0 + 16 * t + col;
-            if (t >= kOutTiles || x >= W) continue;
+            const float d = __fadd_rn(pd2[k], pres[k]);
+            const bool ok = pz[k] > 0.0f && d > 0.0f;
+            dv[k] = ok ? d : 0.0f;
+            fv[k] = (uint8_t)(ok ? (SIMSENSE_FLAG_UNIQUE | SIMSENSE_FLAG_LR | SIMSENSE_FLAG_NONZERO) : 0u);
+        }
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int o = 16 * (t_first + k) + col, x = x0 + o;
+            if (o >= kOutW || x >= W) continue;
             const int64_t p = (int64_t)prow * W + x;
             if (a.out) {
-                float2 o;
-                o.x = pres[k];
-                o.y = pz[k];
-                *(float2 *)(a.out + ((int64_t)img * P + p) * 2) = o;
+                float2 v;
+                v.x = pres[k];
+                v.y = pz[k];
+                *(float2 *)(a.out + ((int64_t)img * P + p) * 2) = v;
             }
             if (a.masked) {
-                const float d = __fadd_rn(pd2[k], pres[k]);
-                const bool ok = pz[k] > 0.0f && d > 0.0f;
-                a.masked[img * a.masked_stride + p] = ok ? d : 0.0f;
-                a.flags[img * a.flags_stride + p] =
-                    (uint8_t)(ok ? (SIMSENSE_FLAG_UNIQUE | SIMSENSE_FLAG_LR | SIMSENSE_FLAG_NONZERO) : 0u);
+                a.masked[img * a.masked_stride + p] = dv[k];
+                a.flags[img * a.flags_stride + p] = fv[k];
             }
         }
     };
-    // the 2-path disparity of tile wave + 4k, column col, clamped into the image
+    // the 2-path disparity of this wave's output tiles, column col, clamped into the image
     const float *d2img = a.d2_sub ? a.d2_sub + img * a.d2_stride : nullptr;
     int d2x[2];
 #pragma unroll
-    for (int k = 0; k < 2; ++k) d2x[k] = min(x0 + 16 * (wave + 4 * k) + col, W - 1);
+    for (int k = 0; k < 2; ++k) d2x[k] = min(max(x0 + 16 * (t_first + k) + col, 0), W - 1);
 
-    for (int r = y0 - 4; r <= y1 + 3; ++r) {
-        const int j4 = r - 4;  // this step's output row
-        __syncthreads();  // the previous step's readers of the feature slot are done
+    // layer-4 partial sums carried from step to step, per tile: row (ky, c) of
+    // the 16-row product holds output channel c of the output row that the
+    // current input row reaches with kernel row ky
+    floatx4 acc4[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+    // register rings of B fragments: [row slot][tile][kx] of layers 2 and 3;
+    // image row r lives in slot (r - s0 + 12) % 3
+    bf16x8 c2[3][2][3], c3[3][2][3];
+
+    auto step = [&](auto phase_c, int s) {
+        constexpr int PH = decltype(phase_c)::value;  // (s - s0) % 3
+        const int j1 = s - D1, j2 = s - D2, j3 = s - D3, j4 = s - D4;
+        __syncthreads();  // every row written last step is complete; its slots' readers are done
+        // Global memory, in an order that never waits on this step's own
+        // accesses: the feature row loaded last step goes to LDS, the previous
+        // step's layer-4 row goes out (with the disparities loaded last step),
+        // then this step's loads are issued; each is consumed a step later.
+        const int r = s + kLead;
+        // one wait for last step's loads (and stores), in every wave, so that no
+        // later point of the step waits on memory
+        __builtin_amdgcn_s_waitcnt((0x7 << 4) | (0xF << 8));
         if (threadIdx.x < kRingW) {
             const bool ok = fq_inside && r >= 0 && r < H;
             if constexpr (FROM_SEL) next = feature_of(next_raw, a.smax, a.max_disp);
-            sm.feat[slot_of(r)][threadIdx.x + 1] = ok ? next : make_uint4(0, 0, 0, 0);
+            sm.feat[slot4(r)][threadIdx.x + 1] = ok ? next : make_uint4(0, 0, 0, 0);
         }
-        if (threadIdx.x < 128) {
+        flush();
+        prow = -1;
+        if (threadIdx.x < kRingW) {
             if constexpr (FROM_SEL) next_raw = fetch_raw(r + 1);
             else next = fetch(r + 1);
         }
-        float d2v[2] = {0.0f, 0.0f};
         if (d2img) {
             const int64_t row = (int64_t)min(max(j4, 0), H - 1) * W;
 #pragma unroll
-            for (int k = 0; k < 2; ++k) d2v[k] = d2img[row + d2x[k]];
+            for (int k = 0; k < 2; ++k) pd2[k] = d2img[row + d2x[k]];
         }
-        flush();
-        __syncthreads();
-        // layer 1, row r - 1 (needed for rows y0-3 .. y1+2)
+
+        // newest input rows of layers 2 and 3 into their register rings
         {
-            const int j = r - 1;
-            if (j >= y0 - 3) {
-                if (j < 0 || j >= H) zero_row(sm, 0, j);
-                else layer_row_any<3, true>(sm, w2, 0, 0, j, xb, W, wave, quad, col);
-            }
+            const int sl1 = slot4(j2 + 1), sl2 = slot4(j3 + 1);
+            constexpr int N2 = (PH + 1) % 3, N3 = (PH + 2) % 3;
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+                for (int kx = 0; kx < 3; ++kx) {
+                    const int p = 16 * (t_first + k) + col + kx;
+                    c2[N2][k][kx] = act_frag(sm, 0, sl1, p, quad);
+                    c3[N3][k][kx] = act_frag(sm, 1, sl2, p, quad);
+                }
         }
-        __syncthreads();
-        {
-            const int j = r - 2;
-            if (j >= y0 - 2 && j <= y1 + 1) {
-                if (j < 0 || j >= H) zero_row(sm, 1, j);
-                else layer_row_any<9, false>(sm, w2, 0, 1, j, xb, W, wave, quad, col);
-            }
+
+        // Every layer runs every step, in one branch-free block, so that one
+        // layer's epilogue and LDS traffic can overlap the next layer's matrix
+        // products.  A row outside the image is stored as zeros (the same
+        // epilogue, with its inside flag false); rows a segment does not need
+        // (warm-up and drain) are computed from whatever the rings hold and
+        // land in ring slots that no needed row is read from.
+        const bool in1 = j1 >= 0 && j1 < H, in2 = j2 >= 0 && j2 < H, in3 = j3 >= 0 && j3 < H;
+        bool colin[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int xq = xb + 16 * (t_first + k) + col;
+            colin[k] = xq >= 0 && xq < W;
         }
-        __syncthreads();
-        {
-            const int j = r - 3;
-            if (j >= y0 - 1 && j <= y1) {
-                if (j < 0 || j >= H) zero_row(sm, 2, j);
-                else layer_row_any<9, false>(sm, w3, 1, 2, j, xb, W, wave, quad, col);
+        // layer-1 B fragments: k = 32 c + 8 quad .. +7 is tap 4 c + quad (zero
+        // beyond the 9 taps), 8 channels, of feature rows j1-1 .. j1+1
+        bf16x8 bf[2][3];
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int tap = 4 * c + quad, tc = tap < 9 ? tap : 8;
+                uint4 v = sm.feat[slot4(j1 - 1 + tc / 3)][16 * (t_first + k) + col + tc % 3];
+                if (tap >= 9) v = make_uint4(0, 0, 0, 0);
+                bf[k][c] = as_bf16x8(v);
             }
-        }
-        __syncthreads();
-        pd2[0] = d2v[0];
-        pd2[1] = d2v[1];
-        prow = -1;
-        // layer 4, row r - 4: 5 output tiles at ring columns kHalo + 16 t
-        if (j4 >= y0 && j4 < y1) {
-            prow = j4;
+        // layer-4 B fragments: the newest layer-3 row (j4 + 1, computed last
+        // step), tiles kHalo columns in, three column shifts
+        bf16x8 bq[2][3];
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx)
+                bq[k][kx] = act_frag(sm, 2, slot4(j4 + 1), kHalo + 16 * (t_first + k) + col + kx, quad);
+
+        // layer 1
+        floatx4 acc1[2][2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb) acc1[k][mb] = bias_acc(sm, 0, mb, quad);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+                for (int mb = 0; mb < 2; ++mb)
+                    acc1[k][mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1[mb][c], bf[k][c], acc1[k][mb], 0, 0, 0);
+
+        // layers 2 and 3 from their register rings: tap c = 3 ky + kx reads ring
+        // slot (F + ky) % 3, F = (PH + 2) % 3 for layer 2 (rows j2-1 .. j2+1) and
+        // PH for layer 3 (rows j3-1 .. j3+1); four independent chains each
+        auto mid_mfma = [&](const bf16x8(&wl)[2][9], const bf16x8(&cache)[3][2][3], auto first_slot, int layer,
+                            floatx4(&acc)[2][2]) {
+            constexpr int F = decltype(first_slot)::value;
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+                for (int mb = 0; mb < 2; ++mb) acc[k][mb] = bias_acc(sm, layer, mb, quad);
+#pragma unroll
+            for (int c = 0; c < 9; ++c)
+#pragma unroll
+                for (int k = 0; k < 2; ++k)
+#pragma unroll
+                    for (int mb = 0; mb < 2; ++mb)
+                        acc[k][mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl[mb][c], cache[(F + c / 3) % 3][k][c % 3],
+                                                                             acc[k][mb], 0, 0, 0);
+        };
+        auto epilogue = [&](int layer, int j, bool rowin, const floatx4(&acc)[2][2]) {
+            const int sl = slot4(j);
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
-                const int t = wave + 4 * k;
-                if (t >= kOutTiles) break;
-                uint4 bv[9];
+                const int q = 16 * (t_first + k) + col;
+                store_relu(sm, layer, sl, q + 1, 0, quad, rowin && colin[k], acc[k][0]);
+                store_relu(sm, layer, sl, q + 1, 1, quad, rowin && colin[k], acc[k][1]);
+            }
+        };
+        floatx4 acc2[2][2];
+        mid_mfma(w2, c2, std::integral_constant<int, (PH + 2) % 3>{}, 1, acc2);
+        epilogue(0, j1, in1, acc1);
+        floatx4 acc3[2][2];
+        mid_mfma(w3, c3, std::integral_constant<int, PH % 3>{}, 2, acc3);
+        epilogue(1, j2, in2, acc2);
+
+        // layer 4 on input row j4 + 1: rows (0, c) start output row j4 + 2 from
+        // the bias, rows (1, c) continue row j4 + 1, rows (2, c) finish row j4
+        // (the per-output order of the products is the per-layer kernel's:
+        // bias, then taps 0..8)
 #pragma unroll
-                for (int c = 0; c < 9; ++c) {
-                    const int pc = kHalo + 16 * t + col + c % 3;
-                    bv[c] = sm.act[2][slot_of(j4 - 1 + c / 3)][pc][swz(pc, quad)];
-                }
-                floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int kx = 0; kx < 3; ++kx)
 #pragma unroll
-                for (int c = 0; c < 9; ++c)
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(sm.w4[col][4 * c + quad]),
-                                                                  as_bf16x8(bv[c]), acc, 0, 0, 0);
-                // lanes of quad 0 hold output channels 0 (residual) and 1 (logit) of pixel col
-                pres[k] = acc[0] + sm.b4[0];
-                pz[k] = acc[1] + sm.b4[1];
-                const int x = x0 + 16 * t + col;
-                if (quad == 0 && x < W) unsure += fabsf(pz[k]) < a.tau ? 1u : 0u;
+            for (int k = 0; k < 2; ++k)
+                acc4[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w4[kx], bq[k][kx], acc4[k], 0, 0, 0);
+        // layer 3's row goes to a slot layer 4 does not read this step
+        epilogue(2, j3, in3, acc3);
+        prow = j4 >= y0 && j4 < y1 ? j4 : -1;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            // lanes of quad 1 hold rows 4, 5 = (2, c): output channels 0 (residual)
+            // and 1 (logit) of row j4, pixel col
+            pres[k] = acc4[k][0];
+            pz[k] = acc4[k][1];
+            const int o = 16 * (t_first + k) + col;
+            if (prow >= 0 && quad == 1 && o < kOutW && x0 + o < W) unsure += fabsf(pz[k]) < a.tau ? 1u : 0u;
+            // move the partial sums one kernel row on: (1, c) -> (2, c) (lanes
+            // 0-15, elements 2, 3 -> lanes 16-31, elements 0, 1), (0, c) -> (1, c),
+            // and (0, c) restarts from the bias
+            const float m2 = __shfl_up(acc4[k][2], 16), m3 = __shfl_up(acc4[k][3], 16);
+            if (quad == 0) {
+                acc4[k][2] = acc4[k][0];
+                acc4[k][3] = acc4[k][1];
+                acc4[k][0] = sm.b4[0];
+                acc4[k][1] = sm.b4[1];
+            } else if (quad == 1) {
+                acc4[k][0] = m2;
+                acc4[k][1] = m3;
             }
         }
+    };
+
+    for (int r = 0; r < nsteps; r += 3) {
+        step(std::integral_constant<int, 0>{}, s0 + r);
+        if (r + 1 < nsteps) step(std::integral_constant<int, 1>{}, s0 + r + 1);
+        if (r + 2 < nsteps) step(std::integral_constant<int, 2>{}, s0 + r + 2);
     }
     flush();
     if (!a.uncertain) return;
@@ -385,10 +463,11 @@ hipError_t launch_infer(InferArgs a, hipStream_t s)
 {
     a.strips = (a.W + kOutW - 1) / kOutW;
     if (a.seg_rows <= 0) {
-        // rows per block: long segments amortise the 4-row warm-up of the
-        // pipeline, short ones give small batches enough blocks (about 1024)
+        // rows per block: long segments amortise the 12-step warm-up and drain
+        // of the pipeline, short ones give small batches enough blocks (one per
+        // compute unit at a time: about 1024 for four rounds)
         const int64_t want = ((int64_t)a.batch * a.strips * a.H + 1023) / 1024;
-        a.seg_rows = (int)std::min<int64_t>(90, std::max<int64_t>(12, want));
+        a.seg_rows = (int)std::min<int64_t>(180, std::max<int64_t>(24, want));
     }
     a.segs = (a.H + a.seg_rows - 1) / a.seg_rows;
     const int64_t blocks = (int64_t)a.batch * a.segs * a.strips;
