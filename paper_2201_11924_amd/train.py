@@ -109,15 +109,20 @@ def load_checkpoint(path: str, net) -> dict:
     return head
 
 
-def build_dataset(runner: PairRunner, raws: List) -> Dict:
+def build_dataset(runner: PairRunner, raws) -> Dict:
+    """Training tensors on the GPU from raw pairs (a list, or an iterable of lists
+    generated chunk by chunk so that the raw images of every pair need not be
+    held on the host at once)."""
     import torch
     feats, tres, tval = [], [], []
-    for raw in raws:
-        s = runner.sample(raw)
-        feats.append(s["features"])
-        tres.append(s["t_res"])
-        tval.append(s["t_valid"])
-    torch.cuda.synchronize()
+    chunks = [raws] if isinstance(raws, list) else raws
+    for chunk in chunks:
+        for raw in chunk:
+            s = runner.sample(raw)
+            feats.append(s["features"])
+            tres.append(s["t_res"])
+            tval.append(s["t_valid"])
+        torch.cuda.synchronize()
     return dict(features=torch.stack(feats), t_res=torch.stack(tres), t_valid=torch.stack(tval))
 
 
@@ -182,21 +187,31 @@ def main(argv=None):
     ap.add_argument("--workers", type=int, default=12)
     ap.add_argument("--out", default=None, help="checkpoint path")
     ap.add_argument("--resume", default=None)
+    ap.add_argument("--chunk", type=int, default=0,
+                    help="generate and convert the training pairs this many at a time (0: all at once)")
+    ap.add_argument("--seed-offset", type=int, default=0,
+                    help="first pair index of the training seeds (pair_seed(3, offset + i))")
     args = ap.parse_args(argv)
     log = lambda s: print(s, flush=True)
 
     cfg = sensor_like(args.width, args.height, args.max_disp)
     t0 = time.time()
-    train_raw = generate([(cfg["spec"], pair_seed(3, i)) for i in range(args.pairs)], args.workers)
+    specs = [(cfg["spec"], pair_seed(3, args.seed_offset + i)) for i in range(args.pairs)]
+    train_raw = generate(specs, args.workers) if args.chunk <= 0 else None
     eval_raw = generate([(cfg["spec"], pair_seed(3, 1_000 + i) + 500_000) for i in range(args.eval_pairs)],
                         args.workers)
-    log(json.dumps({"generated": args.pairs + args.eval_pairs, "s": round(time.time() - t0, 1)}))
+    log(json.dumps({"generated": len(eval_raw) + (len(train_raw) if train_raw else 0), "s": round(time.time() - t0, 1)}))
 
     import torch
     import paper_2201_11924_amd.native as nat
     runner = PairRunner(nat, cfg["params"])
     t0 = time.time()
-    data = build_dataset(runner, train_raw)
+    if train_raw is None:
+        # each chunk is generated by spawned workers when the previous one is converted
+        chunks = (generate(specs[i:i + args.chunk], args.workers) for i in range(0, len(specs), args.chunk))
+        data = build_dataset(runner, chunks)
+    else:
+        data = build_dataset(runner, train_raw)
     del train_raw
     log(json.dumps({"dataset_pairs": int(data["features"].shape[0]), "s": round(time.time() - t0, 1),
                     "valid8_share": float(data["t_valid"].float().mean())}))
