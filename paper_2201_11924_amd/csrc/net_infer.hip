@@ -68,6 +68,15 @@ __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi)
 // pass unchanged; one integer max, with none of the quieting a float max needs
 __device__ __forceinline__ float relu(float v) { return __int_as_float(max(__float_as_int(v), 0)); }
 
+// lanes 16..31 (and 48..63) receive the value of lanes 0..15 (32..47): the
+// swap of the odd 16-lane rows of one operand with the even rows of the other,
+// both operands the same register
+__device__ __forceinline__ float from_row_below(float v)
+{
+    const uint32_t u = __builtin_bit_cast(uint32_t, v);
+    return __builtin_bit_cast(float, __builtin_amdgcn_permlane16_swap(u, u, false, false)[0]);
+}
+
 __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v)
 {
     bf16x8 r;
@@ -78,8 +87,6 @@ __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v)
 struct Smem {
     uint4 feat[kSlots][kRowPx];          // 8 bf16 feature channels per pixel
     uint4 act[3][kSlots][kRowPx][4];     // [layer][slot][pixel][32 bf16 channels, chunks swizzled]
-    float4 bias[3][8];                   // layers 1..3, 32 channels each
-    float b4[2];                         // layer 4, channels 0 and 1
     unsigned count[kWaves];
 };
 
@@ -92,40 +99,49 @@ __device__ __forceinline__ bf16x8 act_frag(const Smem &sm, int layer, int slot, 
     return as_bf16x8(sm.act[layer][slot][p][swz(p, quad)]);
 }
 
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+constexpr int kBufWord3 = 0x00020000;    // buffer resource word 3 for raw byte buffers
+constexpr uint32_t kDrop = 0x80000000u;  // a buffer offset past every plane here: the access is dropped
+
+// ReLU of two bf16 values packed in a word, as two 16-bit integer maxima: a
+// value with its sign bit set (negative, -0, a negative NaN) becomes +0 and the
+// rest pass unchanged.  Rounding to bf16 keeps the sign, so this equals the
+// fp32 ReLU applied before the rounding, bit for bit.
+__device__ __forceinline__ uint32_t relu_pk(uint32_t w)
+{
+    uint32_t r;
+    asm("v_pk_max_i16 %0, %1, 0" : "=v"(r) : "v"(w));
+    return r;
+}
+
 // Epilogue of a 32-channel ReLU layer (the bias is the accumulator's starting
 // value): channels 16 mb + 4 quad .. +3 of ring pixel p (chunk 2 mb + quad / 2,
-// half quad % 2), zero outside the image.
-__device__ __forceinline__ void store_relu(Smem &sm, int layer, int slot, int p, int mb, int quad, bool inside,
+// half quad % 2); keep = all ones inside the image, 0 outside (stored as zeros).
+__device__ __forceinline__ void store_relu(Smem &sm, int layer, int slot, int p, int mb, int quad, uint32_t keep,
                                            const floatx4 &acc)
 {
     uint2 w;
-    w.x = inside ? pack_bf16(relu(acc[0]), relu(acc[1])) : 0u;
-    w.y = inside ? pack_bf16(relu(acc[2]), relu(acc[3])) : 0u;
+    w.x = relu_pk(pack_bf16(acc[0], acc[1])) & keep;
+    w.y = relu_pk(pack_bf16(acc[2], acc[3])) & keep;
     uint2 *dst = (uint2 *)&sm.act[layer][slot][p][0] + 2 * swz(p, 2 * mb + quad / 2) + (quad & 1);
     *dst = w;
-}
-
-// starting value of an accumulator: the layer's biases of channels 16 mb + 4 quad .. +3
-__device__ __forceinline__ floatx4 bias_acc(const Smem &sm, int layer, int mb, int quad)
-{
-    const float4 bv = sm.bias[layer][4 * mb + quad];
-    return floatx4{bv.x, bv.y, bv.z, bv.w};
 }
 
 }  // namespace
 
 // The network's input channels of one pixel from the 2-path selection outputs,
 // evaluated as the features pass does (same float operations, same bf16
-// rounding), so both input routes give the same features bit for bit.
-struct RawFeat {
-    uint32_t ir, s1, s2, d;
-};
-
-__device__ __forceinline__ uint4 feature_of(const RawFeat &v, float smax, int max_disp)
+// rounding), so both input routes give the same features bit for bit.  The
+// work is split in halves, one packed word each: half 0 makes channels 0, 1
+// from (IR, S1), half 1 makes channels 2, 3 from (S2, d*).
+// A half's inputs are one 8-bit and one 16-bit value (IR and S1, or d* and S2).
+__device__ __forceinline__ uint32_t feature_word(int half, uint32_t v8, uint32_t v16, float smax, int max_disp)
 {
-    const float s2 = v.s2 == 0xFFFFu ? smax : fminf((float)v.s2, smax);
-    const float f0 = (float)v.ir / 255.0f, f1 = (float)v.s1 / smax, f2 = s2 / smax, f3 = (float)v.d / (float)max_disp;
-    return make_uint4(pack_bf16(f0, f1), pack_bf16(f2, f3), 0u, 0u);
+    const float x8 = (float)v8, x16 = (float)v16;
+    const float s2 = v16 == 0xFFFFu ? smax : fminf(x16, smax);
+    const float lo = half ? s2 : x8, lo_den = half ? smax : 255.0f;
+    const float hi = half ? x8 : x16, hi_den = half ? (float)max_disp : smax;
+    return pack_bf16(lo / lo_den, hi / hi_den);
 }
 
 template <bool FROM_SEL>
@@ -179,8 +195,34 @@ __global__ __launch_bounds__(256, 1) void net_infer_kernel(InferArgs a)
         if (col < 6) v = *(const uint4 *)(a.w[3] + (col % 2) * kpad(32) + 32 * (3 * (col / 2) + kx) + 8 * quad);
         w4[kx] = as_bf16x8(v);
     }
-    if (threadIdx.x < 96) (&sm.bias[0][0].x)[threadIdx.x] = a.b[threadIdx.x / 32][threadIdx.x % 32];
-    if (threadIdx.x < 2) sm.b4[threadIdx.x] = a.b[3][threadIdx.x];
+    // The weights are used only as MFMA A operands: keep them in the
+    // accumulation registers, which MFMA reads directly, so that the vector
+    // registers stay free for the accumulators and the epilogues (left to
+    // itself the register allocator parks weights there and copies them back
+    // before every use).
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) asm volatile("" : "+a"(w1[mb][c]));
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+            asm volatile("" : "+a"(w2[mb][c]));
+            asm volatile("" : "+a"(w3[mb][c]));
+        }
+    }
+#pragma unroll
+    for (int kx = 0; kx < 3; ++kx) asm volatile("" : "+a"(w4[kx]));
+    // biases (each chain's starting value) in registers: channels 16 mb + 4 quad .. +3
+    floatx4 bias[3][2];
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+            const float *b = a.b[l] + 16 * mb + 4 * quad;
+            bias[l][mb] = floatx4{b[0], b[1], b[2], b[3]};
+        }
+    const float b40 = a.b[3][0], b41 = a.b[3][1];
+    const bool q0 = quad == 0, q1 = quad == 1;
 
     // Wait for the weight loads here, once: otherwise the waits the compiler
     // places before their first use inside the loop would, on every step, also
@@ -198,20 +240,32 @@ __global__ __launch_bounds__(256, 1) void net_infer_kernel(InferArgs a)
     // until the layers have run.  Loads use clamped addresses and are issued
     // unconditionally; out-of-image values are zeroed where they are consumed.
     //
-    // feature rows: thread q < kRingW holds pixel xb + q of the row
+    // Feature rows: threads q and q + 128 (the wave-uniform `half`) handle the
+    // two halves of pixel xb + q of the row: 8 bytes of a given feature map, or
+    // from the selection outputs one packed word of channels each (the raw
+    // values are loaded here and turned into features when they are stored, a
+    // step later, so no load is waited on early).
+    const int half = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 7);
     const int fq = threadIdx.x & (kRingW - 1), fx = min(max(xb + fq, 0), W - 1);
     const bool fq_inside = xb + fq >= 0 && xb + fq < W;
-    auto fetch = [&](int r) { return feat[(int64_t)min(max(r, 0), H - 1) * W + fx]; };
-    // (from the selection outputs: the raw values are loaded here and turned into
-    // features when they are stored, a step later, so no load is waited on early)
-    auto fetch_raw = [&](int r) {
-        const int64_t row = min(max(r, 0), H - 1), p = row * W + fx;
-        RawFeat v;
-        v.ir = irp[row * irpitch + fx];
-        v.s1 = s1i[p];
-        v.s2 = s2i[p];
-        v.d = di[p];
-        return v;
+    // (loads through buffer resources: 32-bit offsets, the bases in scalar registers)
+    const __amdgpu_buffer_rsrc_t rs_feat =
+        __builtin_amdgcn_make_buffer_rsrc((void *)feat, 0, FROM_SEL ? 0 : (int)(16 * P), kBufWord3);
+    auto fetch = [&](int r) {
+        const uint32_t px = (uint32_t)min(max(r, 0), H - 1) * (uint32_t)W + (uint32_t)fx;
+        const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rs_feat, 16 * px + 8 * half, 0, 0);
+        return make_uint2(v[0], v[1]);
+    };
+    const uint8_t *p8 = half ? di : irp;
+    const int64_t pitch8 = half ? (int64_t)W : (int64_t)irpitch;
+    const __amdgpu_buffer_rsrc_t rs16 =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(half ? s2i : s1i), 0, FROM_SEL ? (int)(2 * P) : 0, kBufWord3);
+    auto fetch_raw = [&](int r, uint32_t &v8, uint32_t &v16) {
+        const int row = min(max(r, 0), H - 1);
+        // the 8-bit plane may have a pitch: a resource over the row
+        const __amdgpu_buffer_rsrc_t r8 = __builtin_amdgcn_make_buffer_rsrc((void *)(p8 + row * pitch8), 0, W, kBufWord3);
+        v8 = __builtin_amdgcn_raw_buffer_load_b8(r8, fx, 0, 0);
+        v16 = __builtin_amdgcn_raw_buffer_load_b16(rs16, 2 * ((uint32_t)row * (uint32_t)W + (uint32_t)fx), 0, 0);
     };
 
     // step range: layer 4 (row s - 7) covers rows y0 .. y1-1, so the features
@@ -220,50 +274,57 @@ __global__ __launch_bounds__(256, 1) void net_infer_kernel(InferArgs a)
     const int s0 = y0 - 4 - kLead, s_end = y1 - 1 + D4;
     const int nsteps = s_end - s0 + 1;
 
-    uint4 next = make_uint4(0, 0, 0, 0);
-    RawFeat next_raw{0u, 0u, 0u, 0u};
-    if (threadIdx.x < kRingW) {
-        if constexpr (FROM_SEL) next_raw = fetch_raw(s0 + kLead);
-        else next = fetch(s0 + kLead);
-    }
+    uint2 next = make_uint2(0, 0);
+    uint32_t raw_8 = 0, raw_16 = 0;
+    if constexpr (FROM_SEL) fetch_raw(s0 + kLead, raw_8, raw_16);
+    else next = fetch(s0 + kLead);
     unsigned unsure = 0;
     // layer-4 results of the previous step: row prow (-1: none), this wave's tiles,
     // and the 2-path disparities of that row (loaded during that step)
     float pres[2] = {0.0f, 0.0f}, pz[2] = {0.0f, 0.0f}, pd2[2] = {0.0f, 0.0f};
     int prow = -1;
     const int t_first = 2 * wave;
+    // Outputs and the 2-path disparities go through buffer resources over this
+    // image's planes: an access at an offset past its plane is dropped by the
+    // hardware (a load returns 0), so every lane issues the same accesses and a
+    // step has no branches.  A missing array gets an empty resource.  (Planes
+    // are below 2^31 bytes: 8 bytes x 8192 x 8192 pixels at most.)
+    const int64_t img_px = (int64_t)img * P;
+    const __amdgpu_buffer_rsrc_t rs_out = __builtin_amdgcn_make_buffer_rsrc(
+        a.out ? (void *)(a.out + img_px * 2) : nullptr, 0, a.out ? (int)(8 * P) : 0, kBufWord3);
+    const __amdgpu_buffer_rsrc_t rs_masked = __builtin_amdgcn_make_buffer_rsrc(
+        a.masked ? (void *)(a.masked + img * a.masked_stride) : nullptr, 0, a.masked ? (int)(4 * P) : 0, kBufWord3);
+    const __amdgpu_buffer_rsrc_t rs_flags = __builtin_amdgcn_make_buffer_rsrc(
+        a.masked ? (void *)(a.flags + img * a.flags_stride) : nullptr, 0, a.masked ? (int)P : 0, kBufWord3);
+    const __amdgpu_buffer_rsrc_t rs_d2 = __builtin_amdgcn_make_buffer_rsrc(
+        a.d2_sub ? (void *)(a.d2_sub + img * a.d2_stride) : nullptr, 0, a.d2_sub ? (int)(4 * P) : 0, kBufWord3);
+    // the lanes that write a layer-4 result: quad 1 (rows (2, c) of the
+    // product), output columns of the strip inside the image
+    bool out_lane[2];
+    int out_x[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int o = 16 * (t_first + k) + col;
+        out_x[k] = x0 + o;
+        out_lane[k] = quad == 1 && o < kOutW && x0 + o < W;
+    }
     auto flush = [&]() {
-        if (prow < 0 || quad != 1) return;
-        // every value first (the disparities were loaded a step ago), then the
-        // stores, so that no wait lands between the stores
-        float dv[2];
-        uint8_t fv[2];
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
             const float d = __fadd_rn(pd2[k], pres[k]);
             const bool ok = pz[k] > 0.0f && d > 0.0f;
-            dv[k] = ok ? d : 0.0f;
-            fv[k] = (uint8_t)(ok ? (SIMSENSE_FLAG_UNIQUE | SIMSENSE_FLAG_LR | SIMSENSE_FLAG_NONZERO) : 0u);
-        }
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const int o = 16 * (t_first + k) + col, x = x0 + o;
-            if (o >= kOutW || x >= W) continue;
-            const int64_t p = (int64_t)prow * W + x;
-            if (a.out) {
-                float2 v;
-                v.x = pres[k];
-                v.y = pz[k];
-                *(float2 *)(a.out + ((int64_t)img * P + p) * 2) = v;
-            }
-            if (a.masked) {
-                a.masked[img * a.masked_stride + p] = dv[k];
-                a.flags[img * a.flags_stride + p] = fv[k];
-            }
+            const uint32_t dv = ok ? __builtin_bit_cast(uint32_t, d) : 0u;
+            const uint32_t fv = ok ? (uint32_t)(SIMSENSE_FLAG_UNIQUE | SIMSENSE_FLAG_LR | SIMSENSE_FLAG_NONZERO) : 0u;
+            const bool st = prow >= 0 && out_lane[k];
+            const uint32_t px = (uint32_t)prow * (uint32_t)W + (uint32_t)out_x[k];
+            __builtin_amdgcn_raw_buffer_store_b64(
+                u32x2{__builtin_bit_cast(uint32_t, pres[k]), __builtin_bit_cast(uint32_t, pz[k])}, rs_out,
+                st ? 8 * px : kDrop, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(dv, rs_masked, st ? 4 * px : kDrop, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b8((uint8_t)fv, rs_flags, st ? px : kDrop, 0, 0);
         }
     };
     // the 2-path disparity of this wave's output tiles, column col, clamped into the image
-    const float *d2img = a.d2_sub ? a.d2_sub + img * a.d2_stride : nullptr;
     int d2x[2];
 #pragma unroll
     for (int k = 0; k < 2; ++k) d2x[k] = min(max(x0 + 16 * (t_first + k) + col, 0), W - 1);
@@ -288,21 +349,23 @@ __global__ __launch_bounds__(256, 1) void net_infer_kernel(InferArgs a)
         // one wait for last step's loads (and stores), in every wave, so that no
         // later point of the step waits on memory
         __builtin_amdgcn_s_waitcnt((0x7 << 4) | (0xF << 8));
-        if (threadIdx.x < kRingW) {
-            const bool ok = fq_inside && r >= 0 && r < H;
-            if constexpr (FROM_SEL) next = feature_of(next_raw, a.smax, a.max_disp);
-            sm.feat[slot4(r)][threadIdx.x + 1] = ok ? next : make_uint4(0, 0, 0, 0);
+        const bool fok = fq_inside && r >= 0 && r < H;
+        if constexpr (FROM_SEL) {
+            // (the ring's channels 4..7 keep the zeros they were given at the start)
+            const uint32_t w = feature_word(half, raw_8, raw_16, a.smax, a.max_disp);
+            ((uint32_t *)&sm.feat[slot4(r)][fq + 1])[half] = fok ? w : 0u;
+        } else {
+            ((uint2 *)&sm.feat[slot4(r)][fq + 1])[half] = fok ? next : make_uint2(0, 0);
         }
         flush();
         prow = -1;
-        if (threadIdx.x < kRingW) {
-            if constexpr (FROM_SEL) next_raw = fetch_raw(r + 1);
-            else next = fetch(r + 1);
-        }
-        if (d2img) {
-            const int64_t row = (int64_t)min(max(j4, 0), H - 1) * W;
+        if constexpr (FROM_SEL) fetch_raw(r + 1, raw_8, raw_16);
+        else next = fetch(r + 1);
+        {
+            const uint32_t row = (uint32_t)min(max(j4, 0), H - 1) * (uint32_t)W;
 #pragma unroll
-            for (int k = 0; k < 2; ++k) pd2[k] = d2img[row + d2x[k]];
+            for (int k = 0; k < 2; ++k)
+                pd2[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs_d2, 4 * (row + d2x[k]), 0, 0));
         }
 
         // newest input rows of layers 2 and 3 into their register rings
@@ -341,7 +404,10 @@ __global__ __launch_bounds__(256, 1) void net_infer_kernel(InferArgs a)
             for (int c = 0; c < 3; ++c) {
                 const int tap = 4 * c + quad, tc = tap < 9 ? tap : 8;
                 uint4 v = sm.feat[slot4(j1 - 1 + tc / 3)][16 * (t_first + k) + col + tc % 3];
-                if (tap >= 9) v = make_uint4(0, 0, 0, 0);
+                if (c == 2) {  // taps 9..11 (quads 1..3) are padding: zero, by a mask, not a branch
+                    const uint32_t m = quad == 0 ? ~0u : 0u;
+                    v = make_uint4(v.x & m, v.y & m, v.z & m, v.w & m);
+                }
                 bf[k][c] = as_bf16x8(v);
             }
         // layer-4 B fragments: the newest layer-3 row (j4 + 1, computed last
@@ -353,32 +419,18 @@ __global__ __launch_bounds__(256, 1) void net_infer_kernel(InferArgs a)
             for (int kx = 0; kx < 3; ++kx)
                 bq[k][kx] = act_frag(sm, 2, slot4(j4 + 1), kHalo + 16 * (t_first + k) + col + kx, quad);
 
-        // layer 1
-        floatx4 acc1[2][2];
-#pragma unroll
-        for (int k = 0; k < 2; ++k)
-#pragma unroll
-            for (int mb = 0; mb < 2; ++mb) acc1[k][mb] = bias_acc(sm, 0, mb, quad);
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int k = 0; k < 2; ++k)
-#pragma unroll
-                for (int mb = 0; mb < 2; ++mb)
-                    acc1[k][mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1[mb][c], bf[k][c], acc1[k][mb], 0, 0, 0);
-
-        // layers 2 and 3 from their register rings: tap c = 3 ky + kx reads ring
-        // slot (F + ky) % 3, F = (PH + 2) % 3 for layer 2 (rows j2-1 .. j2+1) and
-        // PH for layer 3 (rows j3-1 .. j3+1); four independent chains each
-        auto mid_mfma = [&](const bf16x8(&wl)[2][9], const bf16x8(&cache)[3][2][3], auto first_slot, int layer,
-                            floatx4(&acc)[2][2]) {
+        // Matrix work, ordered so that the products over input rows already in
+        // registers (layer 2, kernel rows 0 and 1) run while this step's LDS
+        // reads are in flight; each chain still sums bias, tap 0, ..., tap 8 in
+        // that order.  Layers 2 and 3 read tap c = 3 ky + kx from ring slot
+        // (F + ky) % 3, F = (PH + 2) % 3 for layer 2 (rows j2-1 .. j2+1) and PH
+        // for layer 3 (rows j3-1 .. j3+1); four independent chains per layer.
+        floatx4 acc1[2][2], acc2[2][2], acc3[2][2];
+        auto mid_taps = [&](const bf16x8(&wl)[2][9], const bf16x8(&cache)[3][2][3], auto first_slot, auto c_begin,
+                            auto c_end, floatx4(&acc)[2][2]) {
             constexpr int F = decltype(first_slot)::value;
 #pragma unroll
-            for (int k = 0; k < 2; ++k)
-#pragma unroll
-                for (int mb = 0; mb < 2; ++mb) acc[k][mb] = bias_acc(sm, layer, mb, quad);
-#pragma unroll
-            for (int c = 0; c < 9; ++c)
+            for (int c = decltype(c_begin)::value; c < decltype(c_end)::value; ++c)
 #pragma unroll
                 for (int k = 0; k < 2; ++k)
 #pragma unroll
@@ -391,15 +443,41 @@ __global__ __launch_bounds__(256, 1) void net_infer_kernel(InferArgs a)
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
                 const int q = 16 * (t_first + k) + col;
-                store_relu(sm, layer, sl, q + 1, 0, quad, rowin && colin[k], acc[k][0]);
-                store_relu(sm, layer, sl, q + 1, 1, quad, rowin && colin[k], acc[k][1]);
+                const uint32_t keep = rowin && colin[k] ? ~0u : 0u;
+                store_relu(sm, layer, sl, q + 1, 0, quad, keep, acc[k][0]);
+                store_relu(sm, layer, sl, q + 1, 1, quad, keep, acc[k][1]);
             }
         };
-        floatx4 acc2[2][2];
-        mid_mfma(w2, c2, std::integral_constant<int, (PH + 2) % 3>{}, 1, acc2);
+        using F2 = std::integral_constant<int, (PH + 2) % 3>;
+        using F3 = std::integral_constant<int, PH % 3>;
+        using C0 = std::integral_constant<int, 0>;
+        using C6 = std::integral_constant<int, 6>;
+        using C9 = std::integral_constant<int, 9>;
+        auto start = [&](floatx4(&acc)[2][2], int layer) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+                for (int mb = 0; mb < 2; ++mb) acc[k][mb] = bias[layer][mb];
+        };
+        start(acc2, 1);
+        mid_taps(w2, c2, F2{}, C0{}, C6{}, acc2);
+        // (the compiler's scheduler would otherwise hoist layer 1, whose
+        // operands come from LDS, above these products)
+        __builtin_amdgcn_sched_barrier(0);
+        // layer 1
+        start(acc1, 0);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+                for (int mb = 0; mb < 2; ++mb)
+                    acc1[k][mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1[mb][c], bf[k][c], acc1[k][mb], 0, 0, 0);
+        // layer 2's newest input row, then layer 3
+        mid_taps(w2, c2, F2{}, C6{}, C9{}, acc2);
         epilogue(0, j1, in1, acc1);
-        floatx4 acc3[2][2];
-        mid_mfma(w3, c3, std::integral_constant<int, PH % 3>{}, 2, acc3);
+        start(acc3, 2);
+        mid_taps(w3, c3, F3{}, C0{}, C9{}, acc3);
         epilogue(1, j2, in2, acc2);
 
         // layer 4 on input row j4 + 1: rows (0, c) start output row j4 + 2 from
@@ -420,21 +498,16 @@ __global__ __launch_bounds__(256, 1) void net_infer_kernel(InferArgs a)
             // and 1 (logit) of row j4, pixel col
             pres[k] = acc4[k][0];
             pz[k] = acc4[k][1];
-            const int o = 16 * (t_first + k) + col;
-            if (prow >= 0 && quad == 1 && o < kOutW && x0 + o < W) unsure += fabsf(pz[k]) < a.tau ? 1u : 0u;
+            unsure += prow >= 0 && out_lane[k] && fabsf(pz[k]) < a.tau ? 1u : 0u;
             // move the partial sums one kernel row on: (1, c) -> (2, c) (lanes
             // 0-15, elements 2, 3 -> lanes 16-31, elements 0, 1), (0, c) -> (1, c),
             // and (0, c) restarts from the bias
-            const float m2 = __shfl_up(acc4[k][2], 16), m3 = __shfl_up(acc4[k][3], 16);
-            if (quad == 0) {
-                acc4[k][2] = acc4[k][0];
-                acc4[k][3] = acc4[k][1];
-                acc4[k][0] = sm.b4[0];
-                acc4[k][1] = sm.b4[1];
-            } else if (quad == 1) {
-                acc4[k][0] = m2;
-                acc4[k][1] = m3;
-            }
+            const float m2 = from_row_below(acc4[k][2]), m3 = from_row_below(acc4[k][3]);
+            const floatx4 c = acc4[k];
+            acc4[k][0] = q0 ? b40 : q1 ? m2 : c[0];
+            acc4[k][1] = q0 ? b41 : q1 ? m3 : c[1];
+            acc4[k][2] = q0 ? c[0] : c[2];
+            acc4[k][3] = q0 ? c[1] : c[3];
         }
     };
 
