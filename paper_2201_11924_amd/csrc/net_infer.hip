@@ -84,10 +84,17 @@ __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v)
     return r;
 }
 
+// largest feature scale: 8 directions x (census bits + P2 <= 255)
+constexpr int kMaxSmax = 8 * 255;
+
 struct Smem {
     uint4 feat[kSlots][kRowPx];          // 8 bf16 feature channels per pixel
     uint4 act[3][kSlots][kRowPx][4];     // [layer][slot][pixel][32 bf16 channels, chunks swizzled]
     unsigned count[kWaves];
+    // the learned form's feature quotients, i / 255 and i / D (8-bit inputs) and
+    // i / Smax (16-bit inputs, which never exceed Smax)
+    float q8[2][256];
+    float q16[kMaxSmax + 1];
 };
 
 // ring slot of image row r (rows down to -16)
@@ -133,15 +140,15 @@ __device__ __forceinline__ void store_relu(Smem &sm, int layer, int slot, int p,
 // evaluated as the features pass does (same float operations, same bf16
 // rounding), so both input routes give the same features bit for bit.  The
 // work is split in halves, one packed word each: half 0 makes channels 0, 1
-// from (IR, S1), half 1 makes channels 2, 3 from (S2, d*).
-// A half's inputs are one 8-bit and one 16-bit value (IR and S1, or d* and S2).
-__device__ __forceinline__ uint32_t feature_word(int half, uint32_t v8, uint32_t v16, float smax, int max_disp)
+// from (IR, S1), half 1 makes channels 2, 3 from (S2, d*); a half's inputs are
+// one 8-bit and one 16-bit value.  Every numerator is a small integer (IR and
+// d* below 256; S1 <= Smax; S2 <= Smax or "none", which counts as Smax), so the
+// correctly rounded quotients come from tables the block fills once with the
+// same divisions: min(v16, Smax) is the 16-bit index in both halves.
+__device__ __forceinline__ uint32_t feature_word(const Smem &sm, int half, uint32_t v8, uint32_t v16, int smax_i)
 {
-    const float x8 = (float)v8, x16 = (float)v16;
-    const float s2 = v16 == 0xFFFFu ? smax : fminf(x16, smax);
-    const float lo = half ? s2 : x8, lo_den = half ? smax : 255.0f;
-    const float hi = half ? x8 : x16, hi_den = half ? (float)max_disp : smax;
-    return pack_bf16(lo / lo_den, hi / hi_den);
+    const float a = sm.q16[min(v16, (uint32_t)smax_i)], b = sm.q8[half][v8];
+    return half ? pack_bf16(a, b) : pack_bf16(b, a);
 }
 
 template <bool FROM_SEL>
@@ -230,6 +237,14 @@ __global__ __launch_bounds__(256, 1) void net_infer_kernel(InferArgs a)
     // other counters at their maximum.)
     __builtin_amdgcn_s_waitcnt((0x7 << 4) | (0xF << 8));
 
+    const int smax_i = (int)a.smax;
+    if constexpr (FROM_SEL) {
+        for (int i = threadIdx.x; i < 256; i += 256) {
+            sm.q8[0][i] = (float)i / 255.0f;
+            sm.q8[1][i] = (float)i / (float)a.max_disp;
+        }
+        for (int i = threadIdx.x; i <= smax_i; i += 256) sm.q16[i] = (float)i / a.smax;
+    }
     // zero every ring (the zero columns stay zero for good)
     for (int i = threadIdx.x; i < kSlots * kRowPx; i += 256) (&sm.feat[0][0])[i] = make_uint4(0, 0, 0, 0);
     for (int i = threadIdx.x; i < 3 * kSlots * kRowPx * 4; i += 256) (&sm.act[0][0][0][0])[i] = make_uint4(0, 0, 0, 0);
@@ -352,7 +367,7 @@ __global__ __launch_bounds__(256, 1) void net_infer_kernel(InferArgs a)
         const bool fok = fq_inside && r >= 0 && r < H;
         if constexpr (FROM_SEL) {
             // (the ring's channels 4..7 keep the zeros they were given at the start)
-            const uint32_t w = feature_word(half, raw_8, raw_16, a.smax, a.max_disp);
+            const uint32_t w = feature_word(sm, half, raw_8, raw_16, smax_i);
             ((uint32_t *)&sm.feat[slot4(r)][fq + 1])[half] = fok ? w : 0u;
         } else {
             ((uint2 *)&sm.feat[slot4(r)][fq + 1])[half] = fok ? next : make_uint2(0, 0);
@@ -535,12 +550,34 @@ int infer_grid(const InferArgs &a) { return a.batch * a.segs * a.strips; }
 hipError_t launch_infer(InferArgs a, hipStream_t s)
 {
     a.strips = (a.W + kOutW - 1) / kOutW;
+    if (!a.feat && (a.max_disp < 1 || a.max_disp > 256 || !(a.smax >= 1.0f && a.smax <= (float)kMaxSmax) ||
+                    a.smax != (float)(int)a.smax))
+        return hipErrorInvalidValue;  // the feature tables cover these ranges only
     if (a.seg_rows <= 0) {
-        // rows per block: long segments amortise the 12-step warm-up and drain
-        // of the pipeline, short ones give small batches enough blocks (one per
-        // compute unit at a time: about 1024 for four rounds)
-        const int64_t want = ((int64_t)a.batch * a.strips * a.H + 1023) / 1024;
-        a.seg_rows = (int)std::min<int64_t>(180, std::max<int64_t>(24, want));
+        // Rows per block.  One block runs per compute unit at a time and a block
+        // of r rows takes r + 12 steps (the pipeline's warm-up and drain), so
+        // the launch takes about ceil(blocks / CUs) x (r + 12) steps: pick the
+        // number of row segments per image that minimises it.
+        static int num_cus = 0;
+        if (num_cus == 0) {
+            int dev = 0, n = 0;
+            if (hipGetDevice(&dev) == hipSuccess &&
+                hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+                num_cus = n;
+            else
+                num_cus = 256;
+        }
+        const int64_t per_seg = (int64_t)a.batch * a.strips;
+        int64_t best = -1;
+        for (int segs = 1; segs <= a.H; ++segs) {
+            const int rows = (a.H + segs - 1) / segs;
+            if (segs > 1 && (a.H + rows - 1) / rows != segs) continue;  // the same rows as a smaller count
+            const int64_t t = ((per_seg * segs + num_cus - 1) / num_cus) * (rows + 12);
+            if (best < 0 || t < best) {
+                best = t;
+                a.seg_rows = rows;
+            }
+        }
     }
     a.segs = (a.H + a.seg_rows - 1) / a.seg_rows;
     const int64_t blocks = (int64_t)a.batch * a.segs * a.strips;
