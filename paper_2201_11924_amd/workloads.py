@@ -9,7 +9,8 @@ and prints one line; run it under a profiler, for example
 Workloads:
   pair          one 1280x720 pair, D = 128, `--paths` 2/4/8, `--reps` compute calls
   batch         `--pairs` copies of one 1280x720 pair as plain 8-path and as the
-                learned 2-path+net form, one graph launch each per repetition
+                learned 2-path+net form (`--forms` both/learned/plain), one graph
+                launch each per repetition
   net           fused inference of the learned net on `--pairs` 1280x720 feature maps
   train         `--reps` training steps of the learned net on a batch of `--pairs`
                 640x480 feature maps (the training workload's batch shape)
@@ -64,11 +65,14 @@ def run_batch(nat, torch, args):
     b2 = nat.Batch([params2] * n)
     o2 = b2.outputs()
     unc = torch.zeros(n, dtype=torch.int32, device="cuda")
-    b8 = nat.Batch([params8] * n)
-    o8 = b8.outputs()
+    b8 = nat.Batch([params8] * n) if args.forms in ("both", "plain") else None
+    o8 = b8.outputs() if b8 else None
     res = []
-    for name, f in (("learned", lambda: b2.learned_compute(net, Ls, Rs, o2, 0.5, unc)),
-                    ("plain8", lambda: b8.compute(Ls, Rs, o8))):
+    forms = [("learned", lambda: b2.learned_compute(net, Ls, Rs, o2, 0.5, unc)),
+             ("plain8", lambda: b8.compute(Ls, Rs, o8))]
+    for name, f in forms:
+        if args.forms not in ("both", name.rstrip("8")):
+            continue
         f()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -77,7 +81,8 @@ def run_batch(nat, torch, args):
         torch.cuda.synchronize()
         res.append(f"{name} {(time.perf_counter() - t0) / args.reps / n * 1000:.4f} ms/pair")
     b2.close()
-    b8.close()
+    if b8:
+        b8.close()
     net.close()
     return f"batch pairs={n}: " + ", ".join(res)
 
@@ -127,6 +132,8 @@ def main(argv=None):
     ap.add_argument("--paths", type=int, default=8)
     ap.add_argument("--pairs", type=int, default=64)
     ap.add_argument("--reps", type=int, default=4)
+    ap.add_argument("--forms", choices=("both", "learned", "plain"), default="both",
+                    help="batch: which forms to run (256 plain 8-path slots need ~250 GB)")
     args = ap.parse_args(argv)
     import torch
     import paper_2201_11924_amd.native as nat
