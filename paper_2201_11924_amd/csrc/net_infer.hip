@@ -419,7 +419,11 @@ __global__ __launch_bounds__(256, 1) void net_infer_kernel(InferArgs a)
             for (int c = 0; c < 3; ++c) {
                 const int tap = 4 * c + quad, tc = tap < 9 ? tap : 8;
                 uint4 v = sm.feat[slot4(j1 - 1 + tc / 3)][16 * (t_first + k) + col + tc % 3];
-                if (c == 2) {  // taps 9..11 (quads 1..3) are padding: zero, by a mask, not a branch
+                // taps 9..11 (quads 1..3) are padding, whose weights are zero:
+                // features built here are finite, so their products are +0 as
+                // the zeros of the per-layer kernel's padding are; given feature
+                // maps might not be, so those are masked to zero
+                if (c == 2 && !FROM_SEL) {
                     const uint32_t m = quad == 0 ? ~0u : 0u;
                     v = make_uint4(v.x & m, v.y & m, v.z & m, v.w & m);
                 }
