@@ -236,23 +236,28 @@ def test_training_lowers_loss_and_resume_is_exact(nat):
     net.close()
 
 
-def test_features_and_learned_path_match_oracle(nat, orc):
-    """The learned depth path link by link: the 2-path features equal the oracle's
-    bit for bit (float32 quotients rounded to bf16, as the kernel does), the net on
-    them matches the oracle layer by layer within the per-element bounds, and the
-    path's final disparity equals the oracle's combination (float32) and median of
-    the 2-path sub-pixel map and the net output, bit for bit."""
+@pytest.mark.parametrize("paths,census_mode,p2,D", [(2, 0, 86, 64), (4, 1, 150, 96), (8, 0, 200, 128)])
+def test_features_and_learned_path_match_oracle(nat, orc, paths, census_mode, p2, D):
+    """The learned depth path link by link: the features pass equals the oracle's
+    features bit for bit (float32 quotients rounded to bf16, as the kernel does),
+    the net on them matches the oracle layer by layer within the per-element
+    bounds, and the path's final disparity (whose fused kernel builds the features
+    itself from the selection outputs) equals the oracle's combination (float32)
+    and median of the sub-pixel map and the net output, bit for bit.  Besides the
+    2-path form, other path counts, the full census and other penalties change the
+    feature scale Smax = paths x (bits + P2) (234, 848, 1848 here) and the
+    disparity range that the in-kernel feature quotients cover."""
     import torch
     from synth import PairSpec, make_pair
-    W, H, D = 160, 96, 64
-    params2 = dict(width=W, height=H, max_disp=D, census_w=7, census_h=9, census_mode=0, p1=7, p2=86,
-                   uniqueness_pct=10, lr_max_diff=1, num_paths=2, median=3, subpixel=1, focal_px=400.0,
+    W, H = 160, 96
+    params2 = dict(width=W, height=H, max_disp=D, census_w=7, census_h=9, census_mode=census_mode, p1=7, p2=p2,
+                   uniqueness_pct=10, lr_max_diff=1, num_paths=paths, median=3, subpixel=1, focal_px=400.0,
                    baseline_m=0.055)
-    pr = make_pair(PairSpec(W, H, planes=4, dmin=4, dmax=50, noise="gauss", sigma=3.0), 17)
+    pr = make_pair(PairSpec(W, H, planes=4, dmin=4, dmax=min(50, D - 4), noise="gauss", sigma=3.0), 17)
     L = orc.ir_noise(pr.left, pr.gamma_l, pr.n_l)
     R = orc.ir_noise(pr.right, pr.gamma_r, pr.n_r)
     ref2 = orc.sgm(params2, L, R)
-    smax = 2 * (31 + 86)
+    smax = paths * ((62 if census_mode else 31) + p2)
     feats_ref = no.features(L, ref2.s1, ref2.s2, ref2.dint, D, float(smax), dtype=np.float32)
     ss = nat.SimSense(params2)
     g = ss.compute_all(dev(L), dev(R), features=True)
