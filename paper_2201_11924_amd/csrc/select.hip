@@ -46,6 +46,18 @@ constexpr int kSelGroups = kSelBlock / kLanesPerLine;     // pixels in flight pe
 constexpr int sel_ring(int dpl, bool v16, bool small) { return (dpl <= 8 && !v16 && (small || dpl <= 4)) ? 3 : 2; }
 constexpr int sel_waves_per_simd(int dpl, bool v16, bool small) { return sel_ring(dpl, v16, small) == 3 ? 6 : 2; }
 
+// A pointer that lies in global memory.  Pointers read from a device table
+// (the batch form) are generic to the compiler, whose stores through them are
+// then flat stores, which also count on the LDS wait counter; stating the
+// address space lets it emit global stores, as for kernel arguments.
+template <typename T>
+using global_t = __attribute__((address_space(1))) T;
+template <typename T>
+__device__ __forceinline__ global_t<T> *global_ptr(T *p)
+{
+    return (global_t<T> *)p;
+}
+
 template <typename T>
 __device__ __forceinline__ T *uniform_ptr(T *p)
 {
@@ -324,19 +336,23 @@ __device__ __forceinline__ void select_row(const SelectArgs &a, int y, uint32_t 
     }
     __syncthreads();
     const int lr = a.lr_max_diff;
+    global_t<uint8_t> *const o_flags = global_ptr(a.flags), *const o_dint = global_ptr(a.disp_int);
+    global_t<uint8_t> *const o_dright = global_ptr(a.disp_right);
+    global_t<float> *const o_masked = global_ptr(a.masked), *const o_dsub = global_ptr(a.disp_sub);
+    global_t<uint16_t> *const o_s1 = global_ptr(a.cost_best), *const o_s2 = global_ptr(a.cost_second);
     for (int x = threadIdx.x; x < W; x += kSelBlock) {
         const int d = dint_row[x];
         const int xr = x - d;
         bool lr_ok = true;
         if (right && lr >= 0) lr_ok = xr >= 0 && abs(d - (int)(keyR[xr + kDpad] & 0xFF)) <= lr;
         const bool nz = d > 0, uq = uniq_row[x] != 0;
-        a.flags[row + x] = (uint8_t)(uq | (lr_ok << 1) | (nz << 2));
-        a.masked[row + x] = (uq && lr_ok && nz) ? dsub_row[x] : 0.0f;
-        if (right) a.disp_right[row + x] = (uint8_t)(keyR[x + kDpad] & 0xFF);
-        a.disp_int[row + x] = (uint8_t)d;
-        a.cost_best[row + x] = s1_row[x];
-        a.cost_second[row + x] = s2_row[x];
-        a.disp_sub[row + x] = dsub_row[x];
+        o_flags[row + x] = (uint8_t)(uq | (lr_ok << 1) | (nz << 2));
+        o_masked[row + x] = (uq && lr_ok && nz) ? dsub_row[x] : 0.0f;
+        if (right) o_dright[row + x] = (uint8_t)(keyR[x + kDpad] & 0xFF);
+        o_dint[row + x] = (uint8_t)d;
+        o_s1[row + x] = s1_row[x];
+        o_s2[row + x] = s2_row[x];
+        o_dsub[row + x] = dsub_row[x];
     }
 }
 
@@ -434,17 +450,18 @@ __device__ __forceinline__ void post_block(const PostArgs &a, int bx, int by)
     const int x = bx * 64 + threadIdx.x % 64, y = by * 4 + threadIdx.x / 64;
     if (x >= a.W || y >= a.H) return;
     const size_t p = (size_t)y * a.W + x;
-    float v = a.masked[p];
+    const global_t<const float> *const masked = global_ptr((const float *)a.masked);
+    float v = masked[p];
     if (a.median == 3 && x > 0 && y > 0 && x < a.W - 1 && y < a.H - 1) {
         float w[9];
         int k = 0;
         for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) w[k++] = a.masked[p + (ptrdiff_t)dy * a.W + dx];
+            for (int dx = -1; dx <= 1; ++dx) w[k++] = masked[p + (ptrdiff_t)dy * a.W + dx];
         v = median9(w);
     }
-    if (a.disp) a.disp[p] = v;
-    if (a.flags) a.flags[p] = (uint8_t)(a.flags_in[p] | (v > 0.0f ? SIMSENSE_FLAG_VALID : 0u));
-    if (a.depth) a.depth[p] = v > 0.0f ? __fdiv_rn(a.fb, v) : 0.0f;
+    if (a.disp) global_ptr(a.disp)[p] = v;
+    if (a.flags) global_ptr(a.flags)[p] = (uint8_t)(global_ptr(a.flags_in)[p] | (v > 0.0f ? SIMSENSE_FLAG_VALID : 0u));
+    if (a.depth) global_ptr(a.depth)[p] = v > 0.0f ? __fdiv_rn(a.fb, v) : 0.0f;
 }
 
 __global__ __launch_bounds__(256) void post_kernel(PostArgs a) { post_block(a, blockIdx.x, blockIdx.y); }
