@@ -12,6 +12,7 @@
 // (32 k x 16 pixels): a lane then owns 4 consecutive output channels of one
 // pixel, i.e. 8 contiguous bytes of the NHWC output.  The backward-data pass is
 // the same kernel with the taps mirrored and the channel roles swapped.
+#include <algorithm>
 #include <math.h>
 #include <string.h>
 
@@ -164,11 +165,19 @@ hipError_t launch_conv(const ConvArgs &a, int cinp, int coutp, int epi, hipStrea
 
 // ------------------------------------------------------------------ weight gradient
 // dW[co][k] = sum_p dY[p][co] * X[p + tap(k)][ci(k)]: a GEMM with M = COUT, N = 9*CINP
-// and K = pixels.  A block takes a range of image rows; per 32-pixel segment of a
-// row it stages dY transposed ([co][32 px]) and the three input rows transposed
-// ([kx][ci][row][32 px], one copy per horizontal tap offset so that every fragment
-// is one aligned 16-byte LDS read), then each wave accumulates its 16x16 output
-// tiles.  Per-block partial sums are written out and reduced in a fixed order.
+// and K = pixels, on v_mfma_f32_16x16x32_bf16 with dY transposed as the A operand
+// (16 output channels x 32 pixels) and the shifted inputs as the B operand (32
+// pixels x 16 k).  A block owns a 32-pixel column strip of one image over a range
+// of rows and walks down it.  Per output row it takes that row's dY segment and the
+// next input row (34 pixels: the strip and one column each side) with 16-byte
+// loads issued one row ahead, and stores them in LDS transposed (pixels fastest):
+// dY once, the input row three times, shifted by the three horizontal taps, into a
+// ring of three rows, so that every fragment is one aligned 16-byte read and each
+// input row is loaded once.  The bias gradient (the sum of dY over the pixels) is
+// taken from the same staged rows.  Per-block partial sums go out and are reduced
+// in a fixed order, so the result does not depend on the schedule.
+constexpr int kWgradPitch = 32 + 8;  // LDS row pitch in pixels: 16-byte aligned rows
+
 template <int CINP, int COUTP>
 __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a)
 {
@@ -176,128 +185,182 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a)
     constexpr int MB = COUTP / 16;
     constexpr int TILES = MB * NB;
     constexpr int TPW = (TILES + 3) / 4;        // tiles per wave
-    __shared__ __align__(16) uint16_t sdy[32][32];             // [co][px]
-    __shared__ __align__(16) uint16_t sx[3][CINP][3][32];      // [kx][ci][row][px]
+    constexpr int DYC = COUTP / 8, XC = CINP / 8;  // 16-byte chunks per pixel
+    static_assert(32 * DYC <= 256 && 34 * XC <= 272, "one dY and one input chunk per thread (two for 8 threads)");
+    __shared__ __align__(16) uint16_t sdy[COUTP][kWgradPitch];         // [co][px]
+    __shared__ __align__(16) uint16_t sx[3][3][CINP][kWgradPitch];     // [ring slot][kx][ci][px]
+    __shared__ float sbias[256];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int quad = lane >> 4, col = lane & 15;
+    const int W = a.W, H = a.H;
+    const int strips = (W + 31) / 32;
+    int blk = (int)blockIdx.x;
+    const int part_r = blk % a.rsplit;
+    blk /= a.rsplit;
+    const int strip = blk % strips, b = blk / strips;
+    const int y0 = (int)((int64_t)H * part_r / a.rsplit), y1 = (int)((int64_t)H * (part_r + 1) / a.rsplit);
+    const int x0 = 32 * strip;
+    const int64_t img = (int64_t)b * H * W;
+
+    // loader roles: dY chunk (pixel t / DYC, channels 8 (t % DYC) ..) for t < 32 DYC;
+    // input chunk (pixel x0 - 1 + m, m = u / XC, channels 8 (u % XC) ..) for u = t and,
+    // where 34 XC > 256, u = t + 256 for the first threads
+    const int t = threadIdx.x;
+    const bool dy_role = t < 32 * DYC;
+    const int dpx = t / DYC, dch = 8 * (t % DYC);
+    const bool dy_in = dy_role && x0 + dpx < W;
+    auto x_role = [&](int u, int &m, int &ch, bool &valid_col) {
+        m = u / XC;
+        ch = 8 * (u % XC);
+        const int gx = x0 - 1 + m;
+        valid_col = u < 34 * XC && gx >= 0 && gx < W;
+        return u < 34 * XC;
+    };
+    int m0, c0, m1, c1;
+    bool v0, v1;
+    const bool xr0 = x_role(t, m0, c0, v0), xr1 = x_role(t + 256, m1, c1, v1);
+
+    uint4 ndy = make_uint4(0, 0, 0, 0), nx0 = ndy, nx1 = ndy;
+    auto fetch = [&](int it) {
+        // this iteration's rows: input row y0 - 1 + it, dY row y0 - 2 + it
+        const int xrow = y0 - 1 + it, drow = y0 - 2 + it;
+        const uint4 z = make_uint4(0, 0, 0, 0);
+        ndy = dy_in && drow >= y0 ? *(const uint4 *)(a.dy + (img + (int64_t)drow * W + x0 + dpx) * COUTP + dch) : z;
+        const bool row_ok = xrow >= 0 && xrow < H && xrow <= y1;
+        nx0 = v0 && row_ok ? *(const uint4 *)(a.x + (img + (int64_t)xrow * W + x0 - 1 + m0) * CINP + c0) : z;
+        nx1 = v1 && row_ok ? *(const uint4 *)(a.x + (img + (int64_t)xrow * W + x0 - 1 + m1) * CINP + c1) : z;
+    };
+    auto put_x = [&](int slot, int m, int ch, const uint4 &v) {
+        const uint16_t *e = (const uint16_t *)&v;
+#pragma unroll
+        for (int kx = 0; kx < 3; ++kx) {
+            const int j = m - kx;  // copy kx holds input column x0 - 1 + kx + j
+            if (j < 0 || j >= 32) continue;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) sx[slot][kx][ch + i][j] = e[i];
+        }
+    };
+
     floatx4 acc[TPW];
 #pragma unroll
-    for (int t = 0; t < TPW; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int q = 0; q < TPW; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // bias: thread t sums dY of channel t % COUTP over pixels of group t / COUTP
+    constexpr int BG = 256 / COUTP, BPX = 32 / BG;
+    float bsum = 0.0f;
 
-    const int rows = a.batch * a.H;
-    const int r0 = (int)(((int64_t)rows * blockIdx.x) / gridDim.x);
-    const int r1 = (int)(((int64_t)rows * (blockIdx.x + 1)) / gridDim.x);
-    const int segs = (a.W + 31) / 32;
-    for (int r = r0; r < r1; ++r) {
-        const int b = r / a.H, y = r - b * a.H;
-        for (int sg = 0; sg < segs; ++sg) {
-            const int x0 = sg * 32;
-            __syncthreads();
-            // stage dY (COUTP channels, zero past the row end and past COUTP)
-            for (int i = threadIdx.x; i < 32 * 32; i += 256) {
-                const int px = i & 31, co = i >> 5;
-                uint16_t v = 0;
-                if (co < COUTP && x0 + px < a.W) v = a.dy[(((int64_t)b * a.H + y) * a.W + x0 + px) * COUTP + co];
-                sdy[co][px] = v;
-            }
-            // stage X rows y-1..y+1, columns x0-1 .. x0+32, three shifted copies
-            for (int i = threadIdx.x; i < 3 * CINP * 3 * 32; i += 256) {
-                const int px = i & 31;
-                const int rr = (i >> 5) % 3;
-                const int ci = ((i >> 5) / 3) % CINP;
-                const int kx = (i >> 5) / (3 * CINP);
-                const int sy = y + rr - 1, sxx = x0 + px + kx - 1;
-                uint16_t v = 0;
-                if (sy >= 0 && sy < a.H && sxx >= 0 && sxx < a.W && x0 + px < a.W)
-                    v = a.x[(((int64_t)b * a.H + sy) * a.W + sxx) * CINP + ci];
-                sx[kx][ci][rr][px] = v;
-            }
-            __syncthreads();
-            // K-step of 32 pixels: this lane's pixels are 8*quad .. +7
+    const int nit = y1 - y0 + 2;
+    fetch(0);
+    for (int it = 0; it < nit; ++it) {
+        const int xrow = y0 - 1 + it, y = y0 - 2 + it;
+        __syncthreads();  // the previous iteration's reads of sdy and of this ring slot are done
+        const int slot = (xrow + 3) % 3;
+        if (dy_role) {
+            const uint16_t *e = (const uint16_t *)&ndy;
 #pragma unroll
-            for (int t = 0; t < TPW; ++t) {
-                const int tile = wave + 4 * t;
-                if (tile >= TILES) break;
-                const int mb = tile % MB, nb = tile / MB;
-                const bf16x8 av = as_bf16x8(*(const uint4 *)&sdy[16 * mb + col][8 * quad]);
-                const int k = 16 * nb + col;
-                const int tap = k / CINP, ci = k - tap * CINP;
-                uint4 raw = make_uint4(0, 0, 0, 0);
-                if (tap < 9) raw = *(const uint4 *)&sx[tap % 3][ci][tap / 3][8 * quad];
-                const bf16x8 bv = as_bf16x8(raw);
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[t], 0, 0, 0);
-            }
+            for (int i = 0; i < 8; ++i) sdy[dch + i][dpx] = e[i];
         }
+        if (xr0) put_x(slot, m0, c0, nx0);
+        if (xr1) put_x(slot, m1, c1, nx1);
+        if (it + 1 < nit) fetch(it + 1);
+        __syncthreads();
+        if (y < y0) continue;  // ring warm-up: input rows y0 - 1 and y0
+        // output row y reads input rows y-1 .. y+1: ring slots (y + 2 + ky) % 3
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+            const int tile = wave + 4 * q;
+            if (tile >= TILES) break;
+            const int mb = tile % MB, nb = tile / MB;
+            const bf16x8 av = as_bf16x8(*(const uint4 *)&sdy[16 * mb + col][8 * quad]);
+            const int k = 16 * nb + col;
+            const int tap = k / CINP, ci = k - tap * CINP;
+            uint4 raw = make_uint4(0, 0, 0, 0);
+            if (tap < 9) raw = *(const uint4 *)&sx[(y + 2 + tap / 3) % 3][tap % 3][ci][8 * quad];
+            acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, as_bf16x8(raw), acc[q], 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < BPX; ++i) bsum += bf2f(sdy[t % COUTP][BPX * (t / COUTP) + i]);
     }
     // partial[block][co][k]
     float *part = a.partial + (size_t)blockIdx.x * COUTP * 9 * CINP;
 #pragma unroll
-    for (int t = 0; t < TPW; ++t) {
-        const int tile = wave + 4 * t;
+    for (int q = 0; q < TPW; ++q) {
+        const int tile = wave + 4 * q;
         if (tile >= TILES) break;
         const int mb = tile % MB, nb = tile / MB;
         if (16 * nb + col >= 9 * CINP) continue;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) part[(size_t)(16 * mb + 4 * quad + i) * 9 * CINP + 16 * nb + col] = acc[t][i];
+        for (int i = 0; i < 4; ++i) part[(size_t)(16 * mb + 4 * quad + i) * 9 * CINP + 16 * nb + col] = acc[q][i];
     }
-}
-
-// bias gradient partials: partial[block][co] = sum over the block's pixels of dY[p][co]
-template <int COUTP>
-__global__ __launch_bounds__(256) void bgrad_kernel(WgradArgs a)
-{
-    __shared__ float red[256];
-    const int64_t P = (int64_t)a.batch * a.H * a.W;
-    const int co = threadIdx.x % COUTP, lanes = 256 / COUTP, sub = threadIdx.x / COUTP;
-    const int64_t p0 = (P * blockIdx.x) / gridDim.x, p1 = (P * (blockIdx.x + 1)) / gridDim.x;
-    float s = 0.0f;
-    for (int64_t p = p0 + sub; p < p1; p += lanes) s += bf2f(a.dy[p * COUTP + co]);
-    red[threadIdx.x] = s;
+    // bias partial[block][co]: the pixel groups' sums in group order
+    sbias[t] = bsum;
     __syncthreads();
-    if (threadIdx.x < COUTP) {
-        float t = 0.0f;
-        for (int i = 0; i < lanes; ++i) t += red[i * COUTP + threadIdx.x];
-        a.bpartial[(size_t)blockIdx.x * COUTP + threadIdx.x] = t;
+    if (t < COUTP) {
+        float s = 0.0f;
+        for (int g = 0; g < BG; ++g) s += sbias[g * COUTP + t];
+        a.bpartial[(size_t)blockIdx.x * COUTP + t] = s;
     }
 }
 
 // grad[off + ((tap*CIN + ci)*COUT + co)] = sum over blocks of partial[block][co][tap*CINP + ci];
-// grad[boff + co] = sum over blocks of bpartial[block][co]   (fixed order: deterministic)
+// grad[boff + co] = sum over blocks of bpartial[block][co].  A block of 256 threads
+// takes 64 outputs; its 4 thread rows sum quarters of the blocks' partials, each
+// in block order, and the quarters are added in order (deterministic).
 __global__ __launch_bounds__(256) void wgrad_reduce_kernel(WgradReduceArgs a)
 {
+    __shared__ float qs[4][64];
     const int nw = 9 * a.cin * a.cout;
-    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63), qtr = threadIdx.x >> 6;
+    const int b0 = a.nblocks * qtr / 4, b1 = a.nblocks * (qtr + 1) / 4;
+    float s = 0.0f;
     if (i < nw) {
         const int co = i % a.cout, ci = (i / a.cout) % a.cin, tap = i / (a.cout * a.cin);
         const size_t stride = (size_t)a.coutp * 9 * a.cinp;
         const size_t idx = (size_t)co * 9 * a.cinp + tap * a.cinp + ci;
-        float s = 0.0f;
-        for (int blk = 0; blk < a.nblocks; ++blk) s += a.partial[blk * stride + idx];
-        a.grad[a.woff + i] = s;
+        for (int blk = b0; blk < b1; ++blk) s += a.partial[blk * stride + idx];
     } else if (i < nw + a.cout) {
         const int co = i - nw;
-        float s = 0.0f;
-        for (int blk = 0; blk < a.nbblocks; ++blk) s += a.bpartial[(size_t)blk * a.coutp + co];
-        a.grad[a.boff + co] = s;
+        for (int blk = b0; blk < b1; ++blk) s += a.bpartial[(size_t)blk * a.coutp + co];
+    }
+    qs[qtr][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (qtr == 0 && i < nw + a.cout) {
+        const int j = threadIdx.x;
+        const float r = ((qs[0][j] + qs[1][j]) + qs[2][j]) + qs[3][j];
+        if (i < nw) a.grad[a.woff + i] = r;
+        else a.grad[a.boff + (i - nw)] = r;
     }
 }
 
-hipError_t launch_wgrad(const WgradArgs &a, int cinp, int coutp, int nblocks, int nbblocks, hipStream_t s)
+int wgrad_blocks(int batch, int H, int W, int max_blocks, int *rsplit)
 {
-    if (cinp == 8 && coutp == 32) hipLaunchKernelGGL((wgrad_kernel<8, 32>), dim3(nblocks), dim3(256), 0, s, a);
-    else if (cinp == 32 && coutp == 32) hipLaunchKernelGGL((wgrad_kernel<32, 32>), dim3(nblocks), dim3(256), 0, s, a);
-    else if (cinp == 32 && coutp == 16) hipLaunchKernelGGL((wgrad_kernel<32, 16>), dim3(nblocks), dim3(256), 0, s, a);
+    // about 1280 blocks (five rounds of 256 compute units at one block each, in
+    // practice several blocks per unit), each column strip split into row ranges
+    const int64_t cols = (int64_t)batch * ((W + 31) / 32);
+    int64_t r = (1280 + cols - 1) / cols;
+    r = std::max<int64_t>(1, std::min<int64_t>({r, (int64_t)H, max_blocks / std::max<int64_t>(cols, 1)}));
+    *rsplit = (int)r;
+    return (int)(cols * r);
+}
+
+hipError_t launch_wgrad(const WgradArgs &a, int cinp, int coutp, hipStream_t s)
+{
+    const int64_t strips = (a.W + 31) / 32;
+    const int64_t blocks = (int64_t)a.batch * strips * a.rsplit;
+    if (blocks <= 0 || blocks > 0x7FFFFFFF || a.rsplit < 1) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)blocks);
+    if (cinp == 8 && coutp == 32) hipLaunchKernelGGL((wgrad_kernel<8, 32>), grid, dim3(256), 0, s, a);
+    else if (cinp == 32 && coutp == 32) hipLaunchKernelGGL((wgrad_kernel<32, 32>), grid, dim3(256), 0, s, a);
+    else if (cinp == 32 && coutp == 16) hipLaunchKernelGGL((wgrad_kernel<32, 16>), grid, dim3(256), 0, s, a);
     else return hipErrorInvalidValue;
-    if (coutp == 32) hipLaunchKernelGGL((bgrad_kernel<32>), dim3(nbblocks), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((bgrad_kernel<16>), dim3(nbblocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_wgrad_reduce(const WgradReduceArgs &a, hipStream_t s)
 {
     const int n = 9 * a.cin * a.cout + a.cout;
-    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((n + 255) / 256), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((n + 63) / 64), dim3(256), 0, s, a);
     return hipGetLastError();
+
 }
 
 // ------------------------------------------------------------------ loss

@@ -17,7 +17,7 @@ struct LayerShape {
 };
 constexpr LayerShape kLayers[4] = {{4, 32, 8, 32}, {32, 32, 32, 32}, {32, 32, 32, 32}, {32, 2, 32, 16}};
 constexpr int kNumParams = 9 * 4 * 32 + 32 + 2 * (9 * 32 * 32 + 32) + 9 * 32 * 2 + 2;  // 20258
-constexpr int kLossBlocks = 256, kBiasBlocks = 256, kMaxWgradBlocks = 512;
+constexpr int kLossBlocks = 256, kMaxWgradBlocks = 2048;
 
 int woff(int l)
 {
@@ -153,7 +153,7 @@ int simsense_net_create(int64_t max_pixels, uint64_t seed, simsense_net **out)
     sz[k++] = a256(P * 32);          // dy4
     for (int l = 0; l < 3; ++l) sz[k++] = a256(P * 64);  // g[l]
     sz[k++] = a256((size_t)wblocks * 32 * 9 * 32 * sizeof(float));  // wpart
-    sz[k++] = a256((size_t)kBiasBlocks * 32 * sizeof(float));       // bpart
+    sz[k++] = a256((size_t)wblocks * 32 * sizeof(float));           // bpart
     sz[k++] = a256((size_t)kLossBlocks * 3 * sizeof(float));        // lpart
     sz[k++] = a256(3 * sizeof(float));                              // scal
     sz[k++] = a256(3 * sizeof(float));                              // loss
@@ -326,19 +326,19 @@ int simsense_net_train_step(simsense_net *n, const uint16_t *features, const flo
     la.partial = n->lpart; la.scal = n->scal; la.loss = n->loss; la.P = P;
     NET_TRY(launch_loss(la, kLossBlocks, s));
 
-    const int rows = batch * height;
-    const int wblocks = rows < kMaxWgradBlocks ? rows : kMaxWgradBlocks;
+    int rsplit = 1;
+    const int wblocks = wgrad_blocks(batch, height, width, kMaxWgradBlocks, &rsplit);
     // gradient at each layer's output, layer inputs
     const uint16_t *dy = n->dy4;
     const uint16_t *xin[4] = {features, n->act[0], n->act[1], n->act[2]};
     for (int l = 3; l >= 0; --l) {
         WgradArgs wa{};
         wa.x = xin[l]; wa.dy = dy; wa.partial = n->wpart; wa.bpartial = n->bpart;
-        wa.batch = batch; wa.H = height; wa.W = width;
-        NET_TRY(launch_wgrad(wa, kLayers[l].cinp, kLayers[l].coutp, wblocks, kBiasBlocks, s));
+        wa.batch = batch; wa.H = height; wa.W = width; wa.rsplit = rsplit;
+        NET_TRY(launch_wgrad(wa, kLayers[l].cinp, kLayers[l].coutp, s));
         WgradReduceArgs ra{};
         ra.partial = n->wpart; ra.bpartial = n->bpart; ra.grad = n->grad;
-        ra.nblocks = wblocks; ra.nbblocks = kBiasBlocks;
+        ra.nblocks = wblocks; ra.nbblocks = wblocks;
         ra.cin = kLayers[l].cin; ra.cout = kLayers[l].cout; ra.cinp = kLayers[l].cinp; ra.coutp = kLayers[l].coutp;
         ra.woff = woff(l); ra.boff = boff(l);
         NET_TRY(launch_wgrad_reduce(ra, s));

@@ -29,8 +29,9 @@ struct WgradArgs {
     const uint16_t *x;   // layer input, bf16 NHWC CINP channels
     const uint16_t *dy;  // gradient at the layer output, bf16 NHWC COUTP channels
     float *partial;      // [blocks][COUTP][9*CINP]
-    float *bpartial;     // [bias blocks][COUTP]
+    float *bpartial;     // [blocks][COUTP]
     int batch, H, W;
+    int rsplit;          // row ranges per 32-pixel column strip (blocks = batch x strips x rsplit)
 };
 
 struct WgradReduceArgs {
@@ -128,7 +129,9 @@ struct InferArgs {
 
 hipError_t launch_conv(const ConvArgs &a, int cinp, int coutp, int epi, hipStream_t s);
 hipError_t launch_infer(InferArgs a, hipStream_t s);
-hipError_t launch_wgrad(const WgradArgs &a, int cinp, int coutp, int nblocks, int nbblocks, hipStream_t s);
+// blocks of the backward-weight pass for a batch shape (at most max_blocks), and its row split
+int wgrad_blocks(int batch, int H, int W, int max_blocks, int *rsplit);
+hipError_t launch_wgrad(const WgradArgs &a, int cinp, int coutp, hipStream_t s);
 hipError_t launch_wgrad_reduce(const WgradReduceArgs &a, hipStream_t s);
 hipError_t launch_loss(const LossArgs &a, int nblocks, hipStream_t s);
 hipError_t launch_adam(const AdamArgs &a, hipStream_t s);

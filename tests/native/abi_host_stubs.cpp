@@ -36,7 +36,8 @@ int census_tiles(int W, int H) { return ((W + 31) / 32) * ((H + 7) / 8); }
 namespace net {
 STUB(hipError_t launch_conv(const ConvArgs &, int, int, int, hipStream_t))
 STUB(hipError_t launch_infer(InferArgs, hipStream_t))
-STUB(hipError_t launch_wgrad(const WgradArgs &, int, int, int, int, hipStream_t))
+STUB(hipError_t launch_wgrad(const WgradArgs &, int, int, hipStream_t))
+int wgrad_blocks(int, int, int, int, int *rsplit) { *rsplit = 1; return 1; }
 STUB(hipError_t launch_wgrad_reduce(const WgradReduceArgs &, hipStream_t))
 STUB(hipError_t launch_loss(const LossArgs &, int, hipStream_t))
 STUB(hipError_t launch_adam(const AdamArgs &, hipStream_t))
