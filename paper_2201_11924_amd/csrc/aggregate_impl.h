@@ -473,11 +473,17 @@ __device__ __forceinline__ void run_lines(const LineArgs &a, const BlockGeom &g,
     constexpr int kDpad = LPL * DPL;
     constexpr int kLines = kBlock / LPL;                 // lines per block
     constexpr int kSlots = HORIZ ? kLines : kChunk;      // tile slots: lines or clocks
-    constexpr int kSlot = kDpad + 2 * kChunk - 1;        // cR window (Dpad + 15) then cL window (16)
-    constexpr int kTileDw = kSlots * kSlot * kWordDw;
-    constexpr int kLoads = (kTileDw + kBlock - 1) / kBlock;
+    // tile layout (words): the cR windows of all slots (Dpad + 15 words each),
+    // then the cL windows (16 words each)
+    constexpr int kSlotR = kDpad + kChunk - 1;
+    constexpr int kRdw = kSlotR * kWordDw, kLdw = kChunk * kWordDw;  // dwords per window
+    constexpr int kWaves = kBlock / 64;
+    constexpr int kSPW = kSlots / kWaves;                // slots loaded by each wave
+    constexpr int kRl = (kRdw + 63) / 64, kLl = (kSPW * kLdw + 63) / 64;
+    constexpr int kLoads = kSPW * kRl + kLl;             // load instructions per wave and chunk
+    static_assert(kSPW >= 1 && kSlots % kWaves == 0, "every wave loads whole slots");
+    static_assert(kSlots * (kRdw + kLdw) <= TILE, "tile too small");
     static_assert(HORIZ || LPL == kLanesPerLine, "row-sharing lines use one DPP row per line");
-    static_assert(kLoads * kBlock <= TILE, "tile too small");
     const int W = a.W, H = a.H, D = a.D;
     const int lane = threadIdx.x % LPL, li = threadIdx.x / LPL;
     const bool first = lane == 0, last = lane == LPL - 1;
@@ -523,22 +529,49 @@ __device__ __forceinline__ void run_lines(const LineArgs &a, const BlockGeom &g,
             xm = xm0 + (c0 + slot) * g.dx;
         }
     };
-    // direct-to-LDS loads of the chunk starting at clock c0 into ring buffer buf
-    auto stage = [&](int c0, int buf) {
+    // Direct-to-LDS loads of the chunk starting at clock c0 into ring buffer buf.
+    // A window is contiguous in its census map, and the image position of slot s's
+    // window is A0 + c0 * Sc + s * Ss (words), so a lane's byte offset is its lane
+    // index plus a wave-uniform window offset.  Loads go through buffer resources
+    // over the two census maps: a window position outside the image is either
+    // another pixel's word or an offset outside the map (the load returns zero);
+    // such words reach only disparities with x - d < 0, clocks before a line's
+    // start or after its end and lines off the image, whose values the steps
+    // replace or never store.
+    const int lane64 = threadIdx.x & 63;
+    const int s0 = uniform((int)(threadIdx.x >> 6)) * kSPW;
+    const int Sc = HORIZ ? g.dx : g.dy * W + g.dx;
+    const int Ss = HORIZ ? W : Sc;
+    const int A0 = HORIZ ? g.r0 * W + g.xs - (g.dx > 0 ? 0 : kChunk - 1) : row0 * W + xm0;
+    const uint32_t map_bytes = (uint32_t)W * H * kWordDw * 4;
+    const __amdgpu_buffer_rsrc_t rs_cl = __builtin_amdgcn_make_buffer_rsrc((void *)cl, 0, map_bytes, kBufferWord3);
+    const __amdgpu_buffer_rsrc_t rs_cr = __builtin_amdgcn_make_buffer_rsrc((void *)cr, 0, map_bytes, kBufferWord3);
+    // a lane's byte offset within the cL loads, relative to the window of slot s0
+    uint32_t lofs[kLl];
 #pragma unroll
-        for (int k = 0; k < kLoads; ++k) {
-            const int e = threadIdx.x + k * kBlock;  // dword of the tile
-            const int q = e / kWordDw, h = e - q * kWordDw;
-            const int qc = q < kSlots * kSlot ? q : kSlots * kSlot - 1;
-            const int slot = qc / kSlot, idx = qc - slot * kSlot;
-            int row, xm;
-            slot_window(c0, slot, row, xm);
-            const bool is_left = idx >= kDpad + kChunk - 1;
-            int col = is_left ? xm + idx - (kDpad + kChunk - 1) : xm - kDpad + 1 + idx;
-            row = min(max(row, 0), H - 1);
-            col = min(max(col, 0), W - 1);
-            const uint32_t *src = (is_left ? cl : cr) + ((size_t)row * W + col) * kWordDw + h;
-            __builtin_amdgcn_global_load_lds(src, &tile[buf][k * kBlock + (threadIdx.x & ~63)], 4, 0, 0);
+    for (int j = 0; j < kLl; ++j) {
+        const int e = lane64 + 64 * j;
+        lofs[j] = (uint32_t)(((e / kLdw) * Ss * kWordDw + e % kLdw) * 4);
+    }
+    auto stage = [&](int c0, int buf) {
+        const int base = A0 + c0 * Sc + s0 * Ss;  // window position of slot s0
+#pragma unroll
+        for (int i = 0; i < kSPW; ++i) {
+            const int w0 = (base + i * Ss - (kDpad - 1)) * kWordDw * 4;
+#pragma unroll
+            for (int m = 0; m < kRl; ++m) {
+                auto *dst = (__attribute__((address_space(3))) void *)&tile[buf][(s0 + i) * kRdw + 64 * m];
+                const uint32_t vo = (uint32_t)(w0 + 256 * m) + (uint32_t)lane64 * 4;
+                if (64 * (m + 1) <= kRdw || lane64 < kRdw - 64 * m)
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs_cr, dst, 4, vo, 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kLl; ++j) {
+            auto *dst = (__attribute__((address_space(3))) void *)&tile[buf][kSlots * kRdw + s0 * kLdw + 64 * j];
+            const uint32_t vo = (uint32_t)(base * kWordDw * 4) + lofs[j];
+            if (64 * (j + 1) <= kSPW * kLdw || lane64 < kSPW * kLdw - 64 * j)
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rs_cl, dst, 4, vo, 0, 0, 0);
         }
     };
     // lane's pixel, tile slot and window at clock c0 + k
@@ -550,15 +583,16 @@ __device__ __forceinline__ void run_lines(const LineArgs &a, const BlockGeom &g,
     };
     // census words of one clock: cL(x) and cR(x - d) for d = d0 + DPL - 1 .. d0
     auto fetch = [&](int buf, int slot, int xo, Word &wl, Word(&wr)[DPL]) {
-        const Word *sl = (const Word *)&tile[buf][0] + slot * kSlot;
+        const Word *sl = (const Word *)&tile[buf][0] + kSlots * kSlotR + slot * kChunk;  // cL window
+        const Word *sr = (const Word *)&tile[buf][0] + slot * kSlotR;                      // cR window
         if constexpr (WIDE) {
-            wl = sl[kDpad + kChunk - 1 + xo];
-            const Word *p = sl + (xo + kDpad - d0 - DPL);
+            wl = sl[xo];
+            const Word *p = sr + (xo + kDpad - d0 - DPL);
 #pragma unroll
             for (int j = 0; j < DPL; ++j) wr[j] = p[j];
         } else {
-            wl = ds_read_at<0>(lds_addr(sl + kDpad + kChunk - 1 + xo));
-            ds_read_run<DPL>(lds_addr(sl + (xo + kDpad - d0 - DPL)), wr);
+            wl = ds_read_at<0>(lds_addr(sl + xo));
+            ds_read_run<DPL>(lds_addr(sr + (xo + kDpad - d0 - DPL)), wr);
         }
     };
     // the words of a fetch may be used only after this
@@ -596,13 +630,13 @@ __device__ __forceinline__ void run_lines(const LineArgs &a, const BlockGeom &g,
         if constexpr (DPL == 1) {
             (void)idx0;
         } else if constexpr (!WIDE) {
-            uint32_t w[DPL - 1], a0 = lds_addr((const Word *)&tile[0][0] + li * kSlot + idx0);
+            uint32_t w[DPL - 1], a0 = lds_addr((const Word *)&tile[0][0] + li * kSlotR + idx0);
             ds_read_run<DPL - 1>(a0, w);
             lds_wait<DPL - 1>(a0, w);
 #pragma unroll
             for (int i = 0; i < DPL - 1; ++i) win[kFirst + i] = w[i];
         } else {
-            const Word *sl = (const Word *)&tile[0][0] + li * kSlot + idx0;
+            const Word *sl = (const Word *)&tile[0][0] + li * kSlotR + idx0;
 #pragma unroll
             for (int i = 0; i < DPL - 1; ++i) win[kFirst + i] = sl[i];
         }
@@ -647,14 +681,14 @@ __device__ __forceinline__ void run_lines(const LineArgs &a, const BlockGeom &g,
         uint32_t aL = 0, aR = 0;
         if constexpr (!HORIZ && !WIDE) {
             const uint32_t tb = lds_addr(&tile[buf][0]);
-            aL = tb + (uint32_t)(kDpad + kChunk - 1 + xlane) * 4;
+            aL = tb + (uint32_t)(kSlots * kSlotR + xlane) * 4;
             aR = tb + (uint32_t)(xlane + kDpad - d0 - DPL) * 4;
         } else if constexpr (HORIZ && !WIDE) {
             // the line's slot; clock K reads cL at window column xo(K) and the one
             // new cR word (dx > 0: column x - d0; dx < 0: x - d0 - DPL + 1)
-            const uint32_t tb = lds_addr(&tile[buf][0]) + (uint32_t)(li * kSlot) * 4;
-            aL = tb + (uint32_t)(kDpad + kChunk - 1) * 4;
-            aR = tb + (uint32_t)(HDIR > 0 ? kDpad - 1 - d0 : kDpad - d0 - DPL) * 4;
+            const uint32_t tb = lds_addr(&tile[buf][0]);
+            aL = tb + (uint32_t)(kSlots * kSlotR + li * kChunk) * 4;
+            aR = tb + (uint32_t)(li * kSlotR + (HDIR > 0 ? kDpad - 1 - d0 : kDpad - d0 - DPL)) * 4;
         }
         // horizontal lines: cL and the new cR word of clock K
         auto fetch_slide = [&](auto kc, Word &wl, Word(&wn)[1]) {
@@ -664,16 +698,17 @@ __device__ __forceinline__ void run_lines(const LineArgs &a, const BlockGeom &g,
                 wl = ds_read_at<XO * 4>(aL);
                 wn[0] = ds_read_at<XO * 4>(aR);
             } else {
-                const Word *sl = (const Word *)&tile[buf][0] + li * kSlot;
-                wl = sl[kDpad + kChunk - 1 + XO];
-                wn[0] = sl[(HDIR > 0 ? kDpad - 1 - d0 : kDpad - d0 - DPL) + XO];
+                const Word *sl = (const Word *)&tile[buf][0] + kSlots * kSlotR + li * kChunk;
+                const Word *sr = (const Word *)&tile[buf][0] + li * kSlotR;
+                wl = sl[XO];
+                wn[0] = sr[(HDIR > 0 ? kDpad - 1 - d0 : kDpad - d0 - DPL) + XO];
             }
         };
         auto fetch_clock = [&](auto kc, Word &wl, Word(&wr)[DPL]) {
             constexpr int K = decltype(kc)::value;
             if constexpr (!HORIZ && !WIDE) {
-                wl = ds_read_at<K * kSlot * 4>(aL);
-                ds_read_run<DPL, K * kSlot * 4>(aR, wr);
+                wl = ds_read_at<K * kChunk * 4>(aL);
+                ds_read_run<DPL, K * kSlotR * 4>(aR, wr);
             } else {
                 int x, row, xm, slot;
                 locate(c0, K, x, row, xm, slot);

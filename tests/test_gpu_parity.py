@@ -147,14 +147,18 @@ def test_sensor_like_other_sizes(orc, nat):
         compare(orc, nat, cfg["params"], left, right, label=f"{W}x{H}")
 
 
-@pytest.mark.parametrize("W,H,D,paths", [(173, 61, 64, 8), (90, 77, 96, 4), (64, 33, 128, 2)])
-def test_every_launch_shape_matches_oracle(orc, nat, W, H, D, paths):
+@pytest.mark.parametrize("W,H,D,paths,kw", [
+    (173, 61, 64, 8, {}), (90, 77, 96, 4, {}), (64, 33, 128, 2, {}),
+    (150, 41, 128, 8, dict(census_mode=1, p2=60)), (97, 30, 192, 4, {}), (300, 20, 256, 2, dict(census_mode=1, p2=60)),
+])
+def test_every_launch_shape_matches_oracle(orc, nat, W, H, D, paths, kw):
     """Both aggregation launch forms (one block per line block, persistent grid)
-    and every lane count give the oracle's results; autotune keeps the fastest."""
+    and every lane count give the oracle's results, for 32- and 64-bit census
+    words; autotune keeps the fastest."""
     import torch
     spec = PairSpec(W, H, planes=3, dmin=0, dmax=min(D - 1, W - 1) * 0.8, noise="gauss", sigma=3.0)
     left, right = noisy_pair(orc, spec, 7 * W + H)
-    params = params_for(W, H, D, num_paths=paths)
+    params = params_for(W, H, D, num_paths=paths, **kw)
     ref = orc.sgm(params, left, right)
     ss = nat.SimSense(params)
     assert ss.get_tuning() == dict(horizontal_lanes=0, blocks_per_cu=3)
