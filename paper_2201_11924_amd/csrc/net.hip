@@ -50,7 +50,7 @@ __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v)
 
 // ------------------------------------------------------------------ forward / backward-data
 
-constexpr int kConvTilesPerWave = 4;  // 16-pixel tiles per wave (weights stay in registers)
+constexpr int kConvTilesPerWave = 16;  // 16-pixel tiles per wave (weights stay in registers)
 
 template <int CINP, int COUTP, int EPI>
 __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a)
@@ -77,9 +77,12 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a)
 
     const int64_t P = (int64_t)a.batch * a.H * a.W;
     const int64_t tile0 = ((int64_t)blockIdx.x * 4 + wave) * kConvTilesPerWave;
-    for (int tt = 0; tt < kConvTilesPerWave; ++tt) {
-        const int64_t p = (tile0 + tt) * 16 + col;  // this lane's pixel (B operand column)
-        if ((tile0 + tt) * 16 >= P) break;
+    // A lane's B fragments of tile tt (k = 32 c + 8 quad .. +7 of its pixel: zero
+    // outside the image and past the last pixel) and, for the masked epilogue, the
+    // forward activations its outputs are masked by.  The next tile's loads are
+    // issued before this tile's products, so a wave always has loads in flight.
+    auto load_tile = [&](int tt, uint4(&v)[NK], uint2(&mk)[MB]) {
+        const int64_t p = (tile0 + tt) * 16 + col;
         int b = 0, y = 0, x = 0;
         if (p < P) {
             b = (int)(p / ((int64_t)a.H * a.W));
@@ -87,6 +90,31 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a)
             y = r / a.W;
             x = r - y * a.W;
         }
+#pragma unroll
+        for (int c = 0; c < NK; ++c) {
+            const int k8 = 32 * c + 8 * quad;
+            const int tap = k8 / CINP, ch = k8 - tap * CINP;
+            v[c] = make_uint4(0, 0, 0, 0);
+            if (tap < 9 && p < P) {
+                const int sy = y + tap / 3 - 1, sx = x + tap % 3 - 1;
+                if (sy >= 0 && sy < a.H && sx >= 0 && sx < a.W)
+                    v[c] = *(const uint4 *)(a.in + (((int64_t)b * a.H + sy) * a.W + sx) * CINP + ch);
+            }
+        }
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            mk[mb] = make_uint2(0, 0);
+            if (EPI == EPI_MASK && p < P) mk[mb] = *(const uint2 *)(a.mask + p * COUTP + 16 * mb + 4 * quad);
+        }
+    };
+    uint4 v[2][NK];
+    uint2 mk[2][MB];
+    load_tile(0, v[0], mk[0]);
+#pragma unroll
+    for (int tt = 0; tt < kConvTilesPerWave; ++tt) {
+        if ((tile0 + tt) * 16 >= P) break;
+        if (tt + 1 < kConvTilesPerWave) load_tile(tt + 1, v[(tt + 1) & 1], mk[(tt + 1) & 1]);
+        const int64_t p = (tile0 + tt) * 16 + col;  // this lane's pixel (B operand column)
         // the bias is the accumulators' starting value (forward epilogues), so
         // the products are summed onto it in k order
         floatx4 acc[MB];
@@ -96,16 +124,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a)
                                       : floatx4{bias[mb][0], bias[mb][1], bias[mb][2], bias[mb][3]};
 #pragma unroll
         for (int c = 0; c < NK; ++c) {
-            // B fragment: k = 32*c + 8*quad .. +7 of pixel p
-            const int k8 = 32 * c + 8 * quad;
-            const int tap = k8 / CINP, ch = k8 - tap * CINP;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (tap < 9 && p < P) {
-                const int sy = y + tap / 3 - 1, sx = x + tap % 3 - 1;
-                if (sy >= 0 && sy < a.H && sx >= 0 && sx < a.W)
-                    v = *(const uint4 *)(a.in + (((int64_t)b * a.H + sy) * a.W + sx) * CINP + ch);
-            }
-            const bf16x8 bv = as_bf16x8(v);
+            const bf16x8 bv = as_bf16x8(v[tt & 1][c]);
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb)
                 acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[mb][c], bv, acc[mb], 0, 0, 0);
@@ -122,6 +141,8 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a)
                     o[1] = acc[mb][1];
                 }
             } else {
+                const uint16_t m4[4] = {(uint16_t)mk[tt & 1][mb].x, (uint16_t)(mk[tt & 1][mb].x >> 16),
+                                        (uint16_t)mk[tt & 1][mb].y, (uint16_t)(mk[tt & 1][mb].y >> 16)};
                 float h[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
@@ -129,8 +150,8 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a)
                     if (EPI == EPI_RELU) {
                         v = relu(v);
                     } else {
-                        const uint16_t mk = a.mask[p * COUTP + co + i];
-                        v = (mk & 0x7FFF) != 0 && !(mk & 0x8000) ? v : 0.0f;  // mask > 0
+                        const uint16_t m = m4[i];
+                        v = (m & 0x7FFF) != 0 && !(m & 0x8000) ? v : 0.0f;  // mask > 0
                     }
                     h[i] = v;
                 }
@@ -302,32 +323,61 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a)
 }
 
 // grad[off + ((tap*CIN + ci)*COUT + co)] = sum over blocks of partial[block][co][tap*CINP + ci];
-// grad[boff + co] = sum over blocks of bpartial[block][co].  A block of 256 threads
-// takes 64 outputs; its 4 thread rows sum quarters of the blocks' partials, each
-// in block order, and the quarters are added in order (deterministic).
-__global__ __launch_bounds__(256) void wgrad_reduce_kernel(WgradReduceArgs a)
+// grad[boff + co] = sum over blocks of bpartial[block][co].  A block of 1024
+// threads takes 64 consecutive entries of a block's partials (so each load of a
+// wave is one contiguous 256-byte run) and 16 slices of the blocks: a thread sums
+// its slice in block order into four running sums (every fourth block each, for
+// four independent loads in flight), adds them in a fixed order, and the 16
+// slices are added in order (deterministic).  Entries of padding channels are
+// skipped.
+constexpr int kReduceSlices = 16;
+
+__global__ __launch_bounds__(64 * kReduceSlices) void wgrad_reduce_kernel(WgradReduceArgs a)
 {
-    __shared__ float qs[4][64];
-    const int nw = 9 * a.cin * a.cout;
-    const int i = blockIdx.x * 64 + (threadIdx.x & 63), qtr = threadIdx.x >> 6;
-    const int b0 = a.nblocks * qtr / 4, b1 = a.nblocks * (qtr + 1) / 4;
-    float s = 0.0f;
-    if (i < nw) {
-        const int co = i % a.cout, ci = (i / a.cout) % a.cin, tap = i / (a.cout * a.cin);
-        const size_t stride = (size_t)a.coutp * 9 * a.cinp;
-        const size_t idx = (size_t)co * 9 * a.cinp + tap * a.cinp + ci;
-        for (int blk = b0; blk < b1; ++blk) s += a.partial[blk * stride + idx];
-    } else if (i < nw + a.cout) {
-        const int co = i - nw;
-        for (int blk = b0; blk < b1; ++blk) s += a.bpartial[(size_t)blk * a.coutp + co];
+    __shared__ float qs[kReduceSlices][64];
+    const int kw = 9 * a.cinp;                       // entries per output channel
+    const int nw = a.coutp * kw;                     // weight entries per block partial
+    const int e = blockIdx.x * 64 + (threadIdx.x & 63), sl = threadIdx.x >> 6;
+    bool real = false;
+    const float *src = nullptr;
+    size_t stride = 0;
+    int nb = 0, out = 0;
+    if (e < nw) {
+        const int co = e / kw, k = e - co * kw, tap = k / a.cinp, ci = k - tap * a.cinp;
+        real = co < a.cout && ci < a.cin;
+        src = a.partial + e;
+        stride = (size_t)nw;
+        nb = a.nblocks;
+        out = a.woff + (tap * a.cin + ci) * a.cout + co;
+    } else if (e < nw + a.coutp) {
+        const int co = e - nw;
+        real = co < a.cout;
+        src = a.bpartial + co;
+        stride = (size_t)a.coutp;
+        nb = a.nbblocks;
+        out = a.boff + co;
     }
-    qs[qtr][threadIdx.x & 63] = s;
+    float r = 0.0f;
+    if (real) {
+        const int b0 = nb * sl / kReduceSlices, b1 = nb * (sl + 1) / kReduceSlices;
+        float s4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        int blk = b0;
+        for (; blk + 4 <= b1; blk += 4) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) s4[j] += src[(size_t)(blk + j) * stride];
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            if (blk + j < b1) s4[j] += src[(size_t)(blk + j) * stride];
+        r = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+    }
+    qs[sl][threadIdx.x & 63] = r;
     __syncthreads();
-    if (qtr == 0 && i < nw + a.cout) {
-        const int j = threadIdx.x;
-        const float r = ((qs[0][j] + qs[1][j]) + qs[2][j]) + qs[3][j];
-        if (i < nw) a.grad[a.woff + i] = r;
-        else a.grad[a.boff + (i - nw)] = r;
+    if (sl == 0 && real) {
+        float t = qs[0][threadIdx.x];
+#pragma unroll
+        for (int q = 1; q < kReduceSlices; ++q) t += qs[q][threadIdx.x];
+        a.grad[out] = t;
     }
 }
 
@@ -357,8 +407,8 @@ hipError_t launch_wgrad(const WgradArgs &a, int cinp, int coutp, hipStream_t s)
 
 hipError_t launch_wgrad_reduce(const WgradReduceArgs &a, hipStream_t s)
 {
-    const int n = 9 * a.cin * a.cout + a.cout;
-    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((n + 63) / 64), dim3(256), 0, s, a);
+    const int n = 9 * a.cinp * a.coutp + a.coutp;
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((n + 63) / 64), dim3(64 * kReduceSlices), 0, s, a);
     return hipGetLastError();
 
 }
