@@ -191,13 +191,28 @@ hipError_t launch_conv(const ConvArgs &a, int cinp, int coutp, int epi, hipStrea
 // pixels x 16 k).  A block owns a 32-pixel column strip of one image over a range
 // of rows and walks down it.  Per output row it takes that row's dY segment and the
 // next input row (34 pixels: the strip and one column each side) with 16-byte
-// loads issued one row ahead, and stores them in LDS transposed (pixels fastest):
-// dY once, the input row three times, shifted by the three horizontal taps, into a
-// ring of three rows, so that every fragment is one aligned 16-byte read and each
-// input row is loaded once.  The bias gradient (the sum of dY over the pixels) is
-// taken from the same staged rows.  Per-block partial sums go out and are reduced
-// in a fixed order, so the result does not depend on the schedule.
-constexpr int kWgradPitch = 32 + 8;  // LDS row pitch in pixels: 16-byte aligned rows
+// loads issued one row ahead, and stores them in LDS as they are (pixel-major, a
+// ring of three input rows), one 16-byte store per chunk.  The operands, which
+// need 8 consecutive pixels of one channel per lane, are read with the LDS
+// transpose read (ds_read_b64_tr_b16): within 16 lanes, lane 4 j + a reads
+// channels 4 a .. 4 a + 3 of pixel j, and lane n receives channel n of the four
+// pixels; a horizontal tap is a shift of the pixel index, so each input row is
+// stored once.  The bias gradient (the sum of dY over the pixels) is taken from
+// the same staged rows.  Per-block partial sums go out and are reduced in a fixed
+// order, so the result does not depend on the schedule.
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) bf16x4 lds_bf16x4;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kWgBufWord3 = 0x00020000;     // buffer resource word 3 for raw byte buffers
+constexpr uint32_t kWgDrop = 0x80000000u;   // an offset past every map here: the load returns zeros
+
+// four pixels x 16 channels from a pixel-major LDS array, transposed: lane
+// 16 g + n gets channel n of the four pixels (the caller passes, for its lane
+// 4 j + a of the group, the address of channels 4 a .. 4 a + 3 of pixel j)
+__device__ __forceinline__ bf16x4 read_tr(const uint16_t *p)
+{
+    return __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf16x4 *)p);
+}
 
 template <int CINP, int COUTP>
 __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a)
@@ -208,11 +223,12 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a)
     constexpr int TPW = (TILES + 3) / 4;        // tiles per wave
     constexpr int DYC = COUTP / 8, XC = CINP / 8;  // 16-byte chunks per pixel
     static_assert(32 * DYC <= 256 && 34 * XC <= 272, "one dY and one input chunk per thread (two for 8 threads)");
-    __shared__ __align__(16) uint16_t sdy[COUTP][kWgradPitch];         // [co][px]
-    __shared__ __align__(16) uint16_t sx[3][3][CINP][kWgradPitch];     // [ring slot][kx][ci][px]
+    static_assert(CINP % 4 == 0, "a transpose-read lane's four channels share one tap");
+    __shared__ __align__(16) uint16_t sdy[32][COUTP];      // [px][co]
+    __shared__ __align__(16) uint16_t sx[3][34][CINP];     // [ring slot][input column x0 - 1 + m][ci]
     __shared__ float sbias[256];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int quad = lane >> 4, col = lane & 15;
+    const int quad = lane >> 4;
     const int W = a.W, H = a.H;
     const int strips = (W + 31) / 32;
     int blk = (int)blockIdx.x;
@@ -241,26 +257,28 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a)
     bool v0, v1;
     const bool xr0 = x_role(t, m0, c0, v0), xr1 = x_role(t + 256, m1, c1, v1);
 
-    uint4 ndy = make_uint4(0, 0, 0, 0), nx0 = ndy, nx1 = ndy;
+    // loads through buffer resources over this image's maps: a chunk outside the
+    // image or the row range gets an offset past the map, whose load returns zeros
+    const __amdgpu_buffer_rsrc_t rs_dy = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(a.dy + img * COUTP), 0, (int)((int64_t)H * W * COUTP * 2), kWgBufWord3);
+    const __amdgpu_buffer_rsrc_t rs_x = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(a.x + img * CINP), 0, (int)((int64_t)H * W * CINP * 2), kWgBufWord3);
+    u32x4 ndy = {0, 0, 0, 0}, nx0 = ndy, nx1 = ndy;
     auto fetch = [&](int it) {
         // this iteration's rows: input row y0 - 1 + it, dY row y0 - 2 + it
         const int xrow = y0 - 1 + it, drow = y0 - 2 + it;
-        const uint4 z = make_uint4(0, 0, 0, 0);
-        ndy = dy_in && drow >= y0 ? *(const uint4 *)(a.dy + (img + (int64_t)drow * W + x0 + dpx) * COUTP + dch) : z;
+        const uint32_t ody = dy_in && drow >= y0 ? (uint32_t)(((drow * W + x0 + dpx) * COUTP + dch) * 2) : kWgDrop;
         const bool row_ok = xrow >= 0 && xrow < H && xrow <= y1;
-        nx0 = v0 && row_ok ? *(const uint4 *)(a.x + (img + (int64_t)xrow * W + x0 - 1 + m0) * CINP + c0) : z;
-        nx1 = v1 && row_ok ? *(const uint4 *)(a.x + (img + (int64_t)xrow * W + x0 - 1 + m1) * CINP + c1) : z;
+        const uint32_t ox0 = v0 && row_ok ? (uint32_t)(((xrow * W + x0 - 1 + m0) * CINP + c0) * 2) : kWgDrop;
+        const uint32_t ox1 = v1 && row_ok ? (uint32_t)(((xrow * W + x0 - 1 + m1) * CINP + c1) * 2) : kWgDrop;
+        ndy = __builtin_amdgcn_raw_buffer_load_b128(rs_dy, ody, 0, 0);
+        nx0 = __builtin_amdgcn_raw_buffer_load_b128(rs_x, ox0, 0, 0);
+        nx1 = __builtin_amdgcn_raw_buffer_load_b128(rs_x, ox1, 0, 0);
     };
-    auto put_x = [&](int slot, int m, int ch, const uint4 &v) {
-        const uint16_t *e = (const uint16_t *)&v;
-#pragma unroll
-        for (int kx = 0; kx < 3; ++kx) {
-            const int j = m - kx;  // copy kx holds input column x0 - 1 + kx + j
-            if (j < 0 || j >= 32) continue;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) sx[slot][kx][ch + i][j] = e[i];
-        }
-    };
+
+    // transpose-read roles of this lane in its 16-lane group: pixel j of four,
+    // channels (or k) 4 a .. 4 a + 3
+    const int tj = (lane & 15) >> 2, ta = 4 * (lane & 3);
 
     floatx4 acc[TPW];
 #pragma unroll
@@ -275,33 +293,37 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a)
         const int xrow = y0 - 1 + it, y = y0 - 2 + it;
         __syncthreads();  // the previous iteration's reads of sdy and of this ring slot are done
         const int slot = (xrow + 3) % 3;
-        if (dy_role) {
-            const uint16_t *e = (const uint16_t *)&ndy;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) sdy[dch + i][dpx] = e[i];
-        }
-        if (xr0) put_x(slot, m0, c0, nx0);
-        if (xr1) put_x(slot, m1, c1, nx1);
+        if (dy_role) *(u32x4 *)&sdy[dpx][dch] = ndy;
+        if (xr0) *(u32x4 *)&sx[slot][m0][c0] = nx0;
+        if (xr1) *(u32x4 *)&sx[slot][m1][c1] = nx1;
         if (it + 1 < nit) fetch(it + 1);
         __syncthreads();
         if (y < y0) continue;  // ring warm-up: input rows y0 - 1 and y0
-        // output row y reads input rows y-1 .. y+1: ring slots (y + 2 + ky) % 3
+        // output row y reads input rows y-1 .. y+1: ring slots (y + 2 + ky) % 3;
+        // lane group quad takes pixels 8 quad .. 8 quad + 7 (two reads of four)
 #pragma unroll
         for (int q = 0; q < TPW; ++q) {
             const int tile = wave + 4 * q;
             if (tile >= TILES) break;
             const int mb = tile % MB, nb = tile / MB;
-            const bf16x8 av = as_bf16x8(*(const uint4 *)&sdy[16 * mb + col][8 * quad]);
-            const int k = 16 * nb + col;
-            const int tap = k / CINP, ci = k - tap * CINP;
-            uint4 raw = make_uint4(0, 0, 0, 0);
-            if (tap < 9) raw = *(const uint4 *)&sx[(y + 2 + tap / 3) % 3][tap % 3][ci][8 * quad];
-            acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, as_bf16x8(raw), acc[q], 0, 0, 0);
+            const int px = 8 * quad + tj;
+            const bf16x4 a0 = read_tr(&sdy[px][16 * mb + ta]), a1 = read_tr(&sdy[px + 4][16 * mb + ta]);
+            // k columns 16 nb + ta .. +3 share one tap (taps past 8 are padding
+            // columns, whose results are not stored: any in-bounds values do)
+            const int kk = 16 * nb + ta;
+            const int tap = min(kk / CINP, 8), ci = kk % CINP;
+            const uint16_t(*xs)[CINP] = sx[(y + 2 + tap / 3) % 3];
+            const int xm = px + tap % 3;
+            const bf16x4 b0 = read_tr(&xs[xm][ci]), b1 = read_tr(&xs[xm + 4][ci]);
+            const bf16x8 av = __builtin_shufflevector(a0, a1, 0, 1, 2, 3, 4, 5, 6, 7);
+            const bf16x8 bv = __builtin_shufflevector(b0, b1, 0, 1, 2, 3, 4, 5, 6, 7);
+            acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[q], 0, 0, 0);
         }
 #pragma unroll
-        for (int i = 0; i < BPX; ++i) bsum += bf2f(sdy[t % COUTP][BPX * (t / COUTP) + i]);
+        for (int i = 0; i < BPX; ++i) bsum += bf2f(sdy[BPX * (t / COUTP) + i][t % COUTP]);
     }
     // partial[block][co][k]
+    const int col = lane & 15;
     float *part = a.partial + (size_t)blockIdx.x * COUTP * 9 * CINP;
 #pragma unroll
     for (int q = 0; q < TPW; ++q) {
@@ -397,6 +419,8 @@ hipError_t launch_wgrad(const WgradArgs &a, int cinp, int coutp, hipStream_t s)
     const int64_t strips = (a.W + 31) / 32;
     const int64_t blocks = (int64_t)a.batch * strips * a.rsplit;
     if (blocks <= 0 || blocks > 0x7FFFFFFF || a.rsplit < 1) return hipErrorInvalidValue;
+    // the per-image maps are read through buffer resources with 32-bit offsets
+    if ((int64_t)a.H * a.W * std::max(cinp, coutp) * 2 >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
     const dim3 grid((unsigned)blocks);
     if (cinp == 8 && coutp == 32) hipLaunchKernelGGL((wgrad_kernel<8, 32>), grid, dim3(256), 0, s, a);
     else if (cinp == 32 && coutp == 32) hipLaunchKernelGGL((wgrad_kernel<32, 32>), grid, dim3(256), 0, s, a);
