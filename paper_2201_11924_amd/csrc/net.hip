@@ -49,8 +49,25 @@ __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v)
 }
 
 // ------------------------------------------------------------------ forward / backward-data
-
-constexpr int kConvTilesPerWave = 16;  // 16-pixel tiles per wave (weights stay in registers)
+// A 3x3 convolution as an implicit GEMM on v_mfma_f32_16x16x32_bf16: the weights
+// are the A operand (16 output channels x 32 k, k = tap * CINP + ci, held in
+// registers for the block's whole run) and the input the B operand (32 k x 16
+// pixels).  A block owns 64 output columns of one image over 16 rows, taken as 4
+// sub-strips of 4 rows (one row per wave, four 16-pixel tiles each).  For each
+// sub-strip it stages the 6 input rows x 66 columns it reads in LDS (pixel-major,
+// as in memory; positions outside the image are zeros), so every input pixel is
+// loaded once per sub-strip instead of once per tap, and a B fragment (8
+// channels of one pixel and tap) is one aligned 16-byte LDS read.  Each output's
+// products are summed onto its starting value in k order.
+constexpr int kConvCols = 64;   // output columns per block
+constexpr int kConvRows = 4;    // output rows per sub-strip (one per wave)
+constexpr int kConvSubs = 4;    // sub-strips per block
+constexpr int kConvBufWord3 = 0x00020000;    // buffer resource word 3 for raw byte buffers
+constexpr uint32_t kConvDrop = 0x80000000u;  // an offset past every map here: the load returns zeros
+typedef uint32_t u32x4c __attribute__((ext_vector_type(4)));
+// staged pixel pitch in bf16 values: 32 channels are padded to 40 so that the
+// 16-byte reads of 8 consecutive pixels hit 8 different 4-bank groups
+__host__ __device__ constexpr int conv_pitch(int cinp) { return cinp == 32 ? 40 : cinp; }
 
 template <int CINP, int COUTP, int EPI>
 __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a)
@@ -58,6 +75,11 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a)
     constexpr int KPAD = kpad(CINP);
     constexpr int NK = KPAD / 32;
     constexpr int MB = COUTP / 16;
+    constexpr int PP = conv_pitch(CINP);
+    constexpr int SR = kConvRows + 2, SC = kConvCols + 2;  // staged rows and columns
+    constexpr int XC = CINP / 8;                             // 16-byte chunks per pixel
+    constexpr int NCH = SR * SC * XC;                        // chunks per sub-strip
+    __shared__ __align__(16) uint16_t st[SR][SC][PP];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int quad = lane >> 4, col = lane & 15;
     const uint16_t *__restrict__ wk = a.weights;
@@ -75,90 +97,115 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a)
 #pragma unroll
         for (int i = 0; i < 4; ++i) bias[mb][i] = a.bias ? a.bias[16 * mb + 4 * quad + i] : 0.0f;
 
-    const int64_t P = (int64_t)a.batch * a.H * a.W;
-    const int64_t tile0 = ((int64_t)blockIdx.x * 4 + wave) * kConvTilesPerWave;
-    // A lane's B fragments of tile tt (k = 32 c + 8 quad .. +7 of its pixel: zero
-    // outside the image and past the last pixel) and, for the masked epilogue, the
-    // forward activations its outputs are masked by.  The next tile's loads are
-    // issued before this tile's products, so a wave always has loads in flight.
-    auto load_tile = [&](int tt, uint4(&v)[NK], uint2(&mk)[MB]) {
-        const int64_t p = (tile0 + tt) * 16 + col;
-        int b = 0, y = 0, x = 0;
-        if (p < P) {
-            b = (int)(p / ((int64_t)a.H * a.W));
-            const int r = (int)(p - (int64_t)b * a.H * a.W);
-            y = r / a.W;
-            x = r - y * a.W;
-        }
+    const int W = a.W, H = a.H;
+    const int cstrips = (W + kConvCols - 1) / kConvCols;
+    const int rgroups = (H + kConvRows * kConvSubs - 1) / (kConvRows * kConvSubs);
+    int blk = (int)blockIdx.x;
+    const int cs = blk % cstrips;
+    blk /= cstrips;
+    const int rg = blk % rgroups, b = blk / rgroups;
+    const int x0 = cs * kConvCols;
+    const int64_t img = (int64_t)b * H * W;
+    // the image's input map through a buffer resource (32-bit offsets; a position
+    // outside the image gets an offset past the map and loads zeros)
+    const __amdgpu_buffer_rsrc_t rs_in = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(a.in + img * CINP), 0, (int)((int64_t)H * W * CINP * 2), kConvBufWord3);
+    // the B fragment's k = 32 c + 8 quad .. +7 is tap (32 c + 8 quad) / CINP;
+    // taps past 8 are padding (zero weights), read as zeros
+    int tap_r[NK], tap_c[NK], tap_ch[NK];
+    uint32_t tap_keep[NK];
 #pragma unroll
-        for (int c = 0; c < NK; ++c) {
-            const int k8 = 32 * c + 8 * quad;
-            const int tap = k8 / CINP, ch = k8 - tap * CINP;
-            v[c] = make_uint4(0, 0, 0, 0);
-            if (tap < 9 && p < P) {
-                const int sy = y + tap / 3 - 1, sx = x + tap % 3 - 1;
-                if (sy >= 0 && sy < a.H && sx >= 0 && sx < a.W)
-                    v[c] = *(const uint4 *)(a.in + (((int64_t)b * a.H + sy) * a.W + sx) * CINP + ch);
+    for (int c = 0; c < NK; ++c) {
+        const int k8 = 32 * c + 8 * quad, tap = k8 / CINP;
+        const int tc = tap < 9 ? tap : 8;
+        tap_r[c] = tc / 3;
+        tap_c[c] = tc % 3;
+        tap_ch[c] = k8 - tap * CINP;
+        tap_keep[c] = tap < 9 ? ~0u : 0u;
+    }
+
+    for (int sub = 0; sub < kConvSubs; ++sub) {
+        const int y0 = (rg * kConvSubs + sub) * kConvRows;
+        if (y0 >= H) break;
+        __syncthreads();  // the previous sub-strip's reads of the stage are done
+        const int y = y0 + wave;  // this wave's output row
+        // the masked epilogue's forward activations of this wave's four tiles,
+        // loaded while the stage is filled
+        uint2 mk[kConvCols / 16][MB];
+#pragma unroll
+        for (int t = 0; t < kConvCols / 16; ++t)
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                mk[t][mb] = make_uint2(0, 0);
+                const int x = x0 + 16 * t + col;
+                if (EPI == EPI_MASK && y < H && x < W)
+                    mk[t][mb] = *(const uint2 *)(a.mask + (img + (int64_t)y * W + x) * COUTP + 16 * mb + 4 * quad);
             }
+        for (int e = threadIdx.x; e < NCH; e += 256) {
+            const int ch = 8 * (e % XC), pxi = e / XC, c = pxi % SC, r = pxi / SC;
+            const int gy = y0 - 1 + r, gx = x0 - 1 + c;
+            const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
+            const u32x4c v = __builtin_amdgcn_raw_buffer_load_b128(
+                rs_in, in ? (uint32_t)(((gy * W + gx) * CINP + ch) * 2) : kConvDrop, 0, 0);
+            *(u32x4c *)&st[r][c][ch] = v;
         }
+        __syncthreads();
+        if (y >= H) continue;
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-            mk[mb] = make_uint2(0, 0);
-            if (EPI == EPI_MASK && p < P) mk[mb] = *(const uint2 *)(a.mask + p * COUTP + 16 * mb + 4 * quad);
-        }
-    };
-    uint4 v[2][NK];
-    uint2 mk[2][MB];
-    load_tile(0, v[0], mk[0]);
-#pragma unroll
-    for (int tt = 0; tt < kConvTilesPerWave; ++tt) {
-        if ((tile0 + tt) * 16 >= P) break;
-        if (tt + 1 < kConvTilesPerWave) load_tile(tt + 1, v[(tt + 1) & 1], mk[(tt + 1) & 1]);
-        const int64_t p = (tile0 + tt) * 16 + col;  // this lane's pixel (B operand column)
-        // the bias is the accumulators' starting value (forward epilogues), so
-        // the products are summed onto it in k order
-        floatx4 acc[MB];
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
-            acc[mb] = EPI == EPI_MASK ? floatx4{0.f, 0.f, 0.f, 0.f}
-                                      : floatx4{bias[mb][0], bias[mb][1], bias[mb][2], bias[mb][3]};
-#pragma unroll
-        for (int c = 0; c < NK; ++c) {
-            const bf16x8 bv = as_bf16x8(v[tt & 1][c]);
+        for (int t = 0; t < kConvCols / 16; ++t) {
+            const int x = x0 + 16 * t + col;
+            const int64_t p = img + (int64_t)y * W + x;  // this lane's pixel (B operand column)
+            // the bias is the accumulators' starting value (forward epilogues), so
+            // the products are summed onto it in k order
+            floatx4 acc[MB];
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb)
-                acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[mb][c], bv, acc[mb], 0, 0, 0);
-        }
-        if (p >= P) continue;
-        // D layout: lane holds rows (output channels) 4*quad .. +3 of column (pixel) col
+                acc[mb] = EPI == EPI_MASK ? floatx4{0.f, 0.f, 0.f, 0.f}
+                                          : floatx4{bias[mb][0], bias[mb][1], bias[mb][2], bias[mb][3]};
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-            const int co = 16 * mb + 4 * quad;
-            if (EPI == EPI_LINEAR) {
-                if (co == 0) {
-                    float *o = (float *)a.out + p * 2;
-                    o[0] = acc[mb][0];
-                    o[1] = acc[mb][1];
-                }
-            } else {
-                const uint16_t m4[4] = {(uint16_t)mk[tt & 1][mb].x, (uint16_t)(mk[tt & 1][mb].x >> 16),
-                                        (uint16_t)mk[tt & 1][mb].y, (uint16_t)(mk[tt & 1][mb].y >> 16)};
-                float h[4];
+            for (int c = 0; c < NK; ++c) {
+                // staged row wave + ky, column 16 t + col + kx
+                uint4 v = *(const uint4 *)&st[wave + tap_r[c]][16 * t + col + tap_c[c]][tap_ch[c]];
+                v.x &= tap_keep[c];
+                v.y &= tap_keep[c];
+                v.z &= tap_keep[c];
+                v.w &= tap_keep[c];
+                const bf16x8 bv = as_bf16x8(v);
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    float v = acc[mb][i];
-                    if (EPI == EPI_RELU) {
-                        v = relu(v);
-                    } else {
-                        const uint16_t m = m4[i];
-                        v = (m & 0x7FFF) != 0 && !(m & 0x8000) ? v : 0.0f;  // mask > 0
+                for (int mb = 0; mb < MB; ++mb)
+                    acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[mb][c], bv, acc[mb], 0, 0, 0);
+            }
+            if (x >= W) continue;
+            // D layout: lane holds rows (output channels) 4*quad .. +3 of column (pixel) col
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                const int co = 16 * mb + 4 * quad;
+                if (EPI == EPI_LINEAR) {
+                    if (co == 0) {
+                        float *o = (float *)a.out + p * 2;
+                        o[0] = acc[mb][0];
+                        o[1] = acc[mb][1];
                     }
-                    h[i] = v;
+                } else {
+                    const uint2 mw = mk[t][mb];
+                    const uint16_t m4[4] = {(uint16_t)mw.x, (uint16_t)(mw.x >> 16), (uint16_t)mw.y, (uint16_t)(mw.y >> 16)};
+                    float h[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        float v = acc[mb][i];
+                        if (EPI == EPI_RELU) {
+                            v = relu(v);
+                        } else {
+                            const uint16_t m = m4[i];
+                            v = (m & 0x7FFF) != 0 && !(m & 0x8000) ? v : 0.0f;  // mask > 0
+                        }
+                        h[i] = v;
+                    }
+                    uint2 w;
+                    w.x = pack_bf16(h[0], h[1]);
+                    w.y = pack_bf16(h[2], h[3]);
+                    *(uint2 *)((uint16_t *)a.out + p * COUTP + co) = w;
                 }
-                uint2 w;
-                w.x = pack_bf16(h[0], h[1]);
-                w.y = pack_bf16(h[2], h[3]);
-                *(uint2 *)((uint16_t *)a.out + p * COUTP + co) = w;
             }
         }
     }
@@ -166,9 +213,12 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a)
 
 hipError_t launch_conv(const ConvArgs &a, int cinp, int coutp, int epi, hipStream_t s)
 {
-    const int64_t P = (int64_t)a.batch * a.H * a.W;
-    const int64_t tiles = (P + 15) / 16;
-    const int64_t blocks = (tiles + 4 * kConvTilesPerWave - 1) / (4 * kConvTilesPerWave);
+    // the per-image input map is read through a buffer resource with 32-bit offsets
+    if ((int64_t)a.H * a.W * cinp * 2 >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+    const int64_t cstrips = (a.W + kConvCols - 1) / kConvCols;
+    const int64_t rgroups = (a.H + kConvRows * kConvSubs - 1) / (kConvRows * kConvSubs);
+    const int64_t blocks = (int64_t)a.batch * cstrips * rgroups;
+    if (blocks <= 0 || blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
     dim3 grid((unsigned)blocks), block(256);
 #define SS_CONV(CI, CO, E)                                                                \
     if (cinp == CI && coutp == CO && epi == E) {                                          \
