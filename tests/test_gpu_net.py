@@ -102,16 +102,18 @@ def test_forward_layer_by_layer_matches_oracle(nat, B, H, W):
     net.close()
 
 
-def test_training_step_layer_by_layer_matches_oracle(nat):
+@pytest.mark.parametrize("B,H,W", [(2, 12, 40), (1, 37, 150)])
+def test_training_step_layer_by_layer_matches_oracle(nat, B, H, W):
     """One training step, every tensor element by element against the oracle fed
     the GPU's own inputs of that stage: forward layers, the loss gradient at the
     output, the backward-data gradients (with their ReLU masks), and the weight
     and bias gradients (sums over the batch's pixels in fp32: within
-    2 P u32 sum|terms| of the exact sum)."""
+    2 P u32 sum|terms| of the exact sum).  The second size leaves partial
+    convolution windows (64 columns x 16 rows) and backward-weight strips (32
+    columns) on both image edges."""
     import torch
-    B, H, W = 2, 12, 40
     P = B * H * W
-    x, params, t, v = random_case(11, B, H, W)
+    x, params, t, v = random_case(11 + H, B, H, W)
     net = nat.Net(P, seed=3)
     flat0 = no.flatten(params).astype(np.float32)
     net.set_state(flat0)
