@@ -509,14 +509,32 @@ __global__ __launch_bounds__(256) void count_kernel(LossArgs a)
     if (threadIdx.x == 0) a.partial[blockIdx.x * 3 + 1] = red[0];
 }
 
+// the per-block partials j (0: L1, 1: valid count, 2: BCE) summed in a fixed order:
+// thread i takes blocks i nb / 256 .. (i + 1) nb / 256 - 1 in order, then a tree
+__device__ __forceinline__ float reduce_partials(const float *partial, int nblocks, int j, float *red)
+{
+    const int i = threadIdx.x;
+    const int b0 = nblocks * i / 256, b1 = nblocks * (i + 1) / 256;
+    float v = 0.0f;
+    for (int b = b0; b < b1; ++b) v += partial[b * 3 + j];
+    red[i] = v;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (i < st) red[i] += red[i + st];
+        __syncthreads();
+    }
+    return red[0];
+}
+
 __global__ __launch_bounds__(256) void count_reduce_kernel(LossArgs a, int nblocks)
 {
-    if (threadIdx.x != 0) return;
-    float c = 0.0f;
-    for (int i = 0; i < nblocks; ++i) c += a.partial[i * 3 + 1];
-    a.scal[0] = c;
-    a.scal[1] = 1.0f / fmaxf(c, 1.0f);
-    a.scal[2] = 1.0f / (float)a.P;
+    __shared__ float red[256];
+    const float c = reduce_partials(a.partial, nblocks, 1, red);
+    if (threadIdx.x == 0) {
+        a.scal[0] = c;
+        a.scal[1] = 1.0f / fmaxf(c, 1.0f);
+        a.scal[2] = 1.0f / (float)a.P;
+    }
 }
 
 __global__ __launch_bounds__(256) void loss_kernel(LossArgs a)
@@ -556,27 +574,27 @@ __global__ __launch_bounds__(256) void loss_kernel(LossArgs a)
     }
 }
 
-__global__ __launch_bounds__(64) void loss_reduce_kernel(LossArgs a, int nblocks)
+__global__ __launch_bounds__(256) void loss_reduce_kernel(LossArgs a, int nblocks)
 {
-    if (threadIdx.x != 0) return;
-    float l1 = 0.0f, bce = 0.0f;
-    for (int i = 0; i < nblocks; ++i) {
-        l1 += a.partial[i * 3 + 0];
-        bce += a.partial[i * 3 + 2];
+    __shared__ float red[256];
+    float l1 = reduce_partials(a.partial, nblocks, 0, red);
+    __syncthreads();
+    float bce = reduce_partials(a.partial, nblocks, 2, red);
+    if (threadIdx.x == 0) {
+        l1 *= a.scal[1];
+        bce *= a.scal[2];
+        a.loss[0] = l1 + bce;
+        a.loss[1] = l1;
+        a.loss[2] = bce;
     }
-    l1 *= a.scal[1];
-    bce *= a.scal[2];
-    a.loss[0] = l1 + bce;
-    a.loss[1] = l1;
-    a.loss[2] = bce;
 }
 
 hipError_t launch_loss(const LossArgs &a, int nblocks, hipStream_t s)
 {
     hipLaunchKernelGGL(count_kernel, dim3(nblocks), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(count_reduce_kernel, dim3(1), dim3(64), 0, s, a, nblocks);
+    hipLaunchKernelGGL(count_reduce_kernel, dim3(1), dim3(256), 0, s, a, nblocks);
     hipLaunchKernelGGL(loss_kernel, dim3(nblocks), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(64), 0, s, a, nblocks);
+    hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(256), 0, s, a, nblocks);
     return hipGetLastError();
 }
 

@@ -17,7 +17,7 @@ struct LayerShape {
 };
 constexpr LayerShape kLayers[4] = {{4, 32, 8, 32}, {32, 32, 32, 32}, {32, 32, 32, 32}, {32, 2, 32, 16}};
 constexpr int kNumParams = 9 * 4 * 32 + 32 + 2 * (9 * 32 * 32 + 32) + 9 * 32 * 2 + 2;  // 20258
-constexpr int kLossBlocks = 256, kMaxWgradBlocks = 2048;
+constexpr int kLossBlocks = 2048, kMaxWgradBlocks = 2048;
 
 int woff(int l)
 {
