@@ -306,10 +306,9 @@ int enqueue_match(simsense_handle *h, const uint8_t *left, const uint8_t *right,
     TraceRange range("simsense match");
     profile_mark(h, SIMSENSE_PASS_CENSUS, false, s);
     const bool queue = !h->sgbm && h->tuning.blocks_per_cu > 0;
-    SS_TRY(launch_census(left, pitch, W, H, p.census_w, p.census_h, p.census_mode, h->census_l, h->wide, s));
-    // (the second census launch also clears the work-queue counter)
-    SS_TRY(launch_census(right, pitch, W, H, p.census_w, p.census_h, p.census_mode, h->census_r, h->wide, s,
-                         queue ? h->d_counter : nullptr, queue ? 1 : 0));
+    // (the census launch also clears the work-queue counter)
+    SS_TRY(launch_census_pair(left, right, pitch, W, H, p.census_w, p.census_h, p.census_mode, h->census_l,
+                              h->census_r, h->wide, s, queue ? h->d_counter : nullptr, queue ? 1 : 0));
     profile_mark(h, SIMSENSE_PASS_CENSUS, true, s);
 
     const AggregateArgs ag = handle_aggregate_args(h);

@@ -148,14 +148,18 @@ __device__ __forceinline__ void census_any(const uint8_t *img, int pitch, int W,
     census_tile<Word>(img, pitch, W, H, cw, ch, mode, out, bx, by, tile);
 }
 
+// one launch for one or two images of the same size (blockIdx.z picks the image)
 template <typename Word>
-__global__ __launch_bounds__(256) void census_kernel(const uint8_t *__restrict__ img, int pitch, int W, int H, int cw,
-                                                     int ch, int mode, Word *__restrict__ out, unsigned *zero, int nzero)
+__global__ __launch_bounds__(256) void census_kernel(const uint8_t *__restrict__ img0, const uint8_t *__restrict__ img1,
+                                                     int pitch, int W, int H, int cw, int ch, int mode,
+                                                     Word *__restrict__ out0, Word *__restrict__ out1, unsigned *zero,
+                                                     int nzero)
 {
     extern __shared__ uint8_t tile[];
     const int tid = threadIdx.y * kCensusTx + threadIdx.x;
-    if (blockIdx.x == 0 && blockIdx.y == 0 && tid < nzero) zero[tid] = 0u;
-    census_any<Word>(img, pitch, W, H, cw, ch, mode, out, blockIdx.x, blockIdx.y, tile);
+    if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && tid < nzero) zero[tid] = 0u;
+    const bool second = blockIdx.z != 0;
+    census_any<Word>(second ? img1 : img0, pitch, W, H, cw, ch, mode, second ? out1 : out0, blockIdx.x, blockIdx.y, tile);
 }
 
 // batch form: one block per (job, 32x8 tile) item; tile = by * ceil(W/32) + bx
@@ -185,20 +189,26 @@ hipError_t launch_census_batch(const CensusBatch &b, bool out64, hipStream_t s)
 
 int census_tiles(int W, int H) { return ((W + kCensusTx - 1) / kCensusTx) * ((H + kCensusTy - 1) / kCensusTy); }
 
-hipError_t launch_census(const uint8_t *img, int pitch, int W, int H, int cw, int ch, int mode, void *out,
-                         bool out64, hipStream_t s, unsigned *zero, int nzero)
+hipError_t launch_census_pair(const uint8_t *img0, const uint8_t *img1, int pitch, int W, int H, int cw, int ch,
+                              int mode, void *out0, void *out1, bool out64, hipStream_t s, unsigned *zero, int nzero)
 {
     if (nzero < 0 || nzero > kCensusTx * kCensusTy || (nzero > 0 && !zero)) return hipErrorInvalidValue;
-    dim3 grid((W + kCensusTx - 1) / kCensusTx, (H + kCensusTy - 1) / kCensusTy);
+    dim3 grid((W + kCensusTx - 1) / kCensusTx, (H + kCensusTy - 1) / kCensusTy, img1 ? 2 : 1);
     dim3 block(kCensusTx, kCensusTy);
     size_t lds = (size_t)(kCensusTx + cw - 1) * (kCensusTy + ch - 1);
     if (out64)
-        hipLaunchKernelGGL(census_kernel<uint64_t>, grid, block, lds, s, img, pitch, W, H, cw, ch, mode,
-                           (uint64_t *)out, zero, nzero);
+        hipLaunchKernelGGL(census_kernel<uint64_t>, grid, block, lds, s, img0, img1, pitch, W, H, cw, ch, mode,
+                           (uint64_t *)out0, (uint64_t *)out1, zero, nzero);
     else
-        hipLaunchKernelGGL(census_kernel<uint32_t>, grid, block, lds, s, img, pitch, W, H, cw, ch, mode,
-                           (uint32_t *)out, zero, nzero);
+        hipLaunchKernelGGL(census_kernel<uint32_t>, grid, block, lds, s, img0, img1, pitch, W, H, cw, ch, mode,
+                           (uint32_t *)out0, (uint32_t *)out1, zero, nzero);
     return hipGetLastError();
+}
+
+hipError_t launch_census(const uint8_t *img, int pitch, int W, int H, int cw, int ch, int mode, void *out,
+                         bool out64, hipStream_t s, unsigned *zero, int nzero)
+{
+    return launch_census_pair(img, nullptr, pitch, W, H, cw, ch, mode, out, nullptr, out64, s, zero, nzero);
 }
 
 }  // namespace ss

@@ -82,6 +82,10 @@ hipError_t launch_ir_noise(const uint8_t *in, const float *gamma, const float *n
 // launch that follows needs no kernel of its own for that)
 hipError_t launch_census(const uint8_t *img, int pitch, int W, int H, int cw, int ch, int mode,
                          void *out, bool out64, hipStream_t s, unsigned *zero = nullptr, int nzero = 0);
+// both images of a pair in one launch (img1 may be null: img0 alone)
+hipError_t launch_census_pair(const uint8_t *img0, const uint8_t *img1, int pitch, int W, int H, int cw, int ch,
+                              int mode, void *out0, void *out1, bool out64, hipStream_t s, unsigned *zero = nullptr,
+                              int nzero = 0);
 struct AggregateQueue {
     const AggregateArgs *slots;  // per pair slot (device)
     const uint32_t *items;       // slot << 20 | block, longest first (device)

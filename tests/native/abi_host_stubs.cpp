@@ -18,6 +18,8 @@ STUB(hipError_t launch_agg_dpl8(const AggregateArgs *, const AggregateQueue *, i
 STUB(hipError_t launch_agg_dpl12(const AggregateArgs *, const AggregateQueue *, int, int, bool, hipStream_t))
 STUB(hipError_t launch_agg_dpl16(const AggregateArgs *, const AggregateQueue *, int, int, bool, hipStream_t))
 STUB(hipError_t launch_census(const uint8_t *, int, int, int, int, int, int, void *, bool, hipStream_t, unsigned *, int))
+STUB(hipError_t launch_census_pair(const uint8_t *, const uint8_t *, int, int, int, int, int, int, void *, void *, bool,
+                                   hipStream_t, unsigned *, int))
 STUB(hipError_t launch_census_batch(const CensusBatch &, bool, hipStream_t))
 STUB(hipError_t launch_ir_noise(const uint8_t *, const float *, const float *, uint8_t *, int64_t, hipStream_t))
 STUB(hipError_t launch_select(const SelectArgs &, hipStream_t))
