@@ -5,8 +5,12 @@
 //   counter reset -> census (every image) -> aggregation (a persistent kernel per
 //   padded-disparity group, pulling line blocks from a longest-first queue) ->
 //   selection (per group) -> median/depth.
-// The pass sequence is captured once into a graph; a compute call only refreshes
-// the image/output pointer tables (one host-to-device copy) and launches the graph.
+// The slots are split into phases of consecutive slots; each phase runs the pass
+// sequence on its own, on one of two streams in turn, and a phase's aggregation
+// starts when the previous phase's has finished, so that it runs while that phase
+// selects (bound by HBM) and the vector ALUs and HBM are busy at once.  The pass
+// sequence is captured once into a graph; a compute call only refreshes the
+// image/output pointer tables (one host-to-device copy) and launches the graph.
 #include <algorithm>
 #include <map>
 #include <new>
@@ -31,6 +35,14 @@ struct Slot {
 };
 
 size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// phases the plain form of a batch of n slots is split into (consecutive slots, as
+// equal in number as can be; one phase for a single slot).  Measured at 64 and 256
+// sensor pairs: 4 phases 5% more pairs/s than 1 for the plain form; the learned
+// form, whose fused-net blocks need a whole unit, runs as one phase (4 phases: 4%
+// fewer pairs/s).
+constexpr int kBatchPhases = 4;
+int batch_phases(int n) { return std::min(n, kBatchPhases); }
 
 }  // namespace
 
@@ -57,13 +69,22 @@ struct simsense_batch {
     // launch plan
     struct AggGroup { int dpad, hl; bool wide; size_t item_off; int nitems; int counter; };
     struct SelGroup { int dpad, ndirs; bool small; size_t item_off; int nitems; };
+    // a phase: slots s0 .. s1-1, their item lists and groups (ranges of the vectors)
+    struct Phase {
+        int s0, s1;
+        size_t census_item_off, post_item_off;
+        int census_nitems, post_nitems;
+        int agg0, nagg, sel0, nsel;
+    };
     std::vector<AggGroup> agg_groups;
     std::vector<SelGroup> sel_groups;
-    size_t census_item_off, post_item_off;
-    int census_nitems, post_nitems, max_cw, max_ch, max_w;
+    std::vector<Phase> phases;   // the plain form's
+    std::vector<Phase> lphases;  // the learned form's (one phase: its net blocks do not share a unit)
+    int max_cw, max_ch, max_w;
     bool census_wide;
-    // graph
-    hipStream_t capture_stream;
+    // graph (the second stream and the events join the capture of the first)
+    hipStream_t capture_stream, side_stream;
+    hipEvent_t ev_fork, ev_join, ev_agg[kBatchPhases];
     hipGraphExec_t exec;
     bool captured;
     hipStream_t last_stream;
@@ -94,8 +115,7 @@ int build_plan(simsense_batch *b)
     std::vector<uint32_t> items;
     b->agg_groups.clear();
     b->sel_groups.clear();
-    // census: every image
-    b->census_item_off = items.size();
+    b->phases.clear();
     b->max_cw = b->max_ch = 1;
     b->max_w = 1;
     for (int s = 0; s < n; ++s) {
@@ -103,97 +123,123 @@ int build_plan(simsense_batch *b)
         b->max_cw = std::max(b->max_cw, sl.p.census_w);
         b->max_ch = std::max(b->max_ch, sl.p.census_h);
         b->max_w = std::max(b->max_w, sl.p.width);
-        const int t = census_tiles(sl.p.width, sl.p.height);
-        for (int img = 0; img < 2; ++img)
-            for (int i = 0; i < t; ++i) items.push_back(((uint32_t)(2 * s + img) << 20) | (uint32_t)i);
     }
-    b->census_nitems = (int)(items.size() - b->census_item_off);
-    // aggregation: group slots by (Dpad, wide); items largest estimated work first
     std::vector<AggregateArgs> agg(n);
-    std::map<std::pair<int, bool>, std::vector<std::pair<int, uint32_t>>> groups;
-    for (int s = 0; s < n; ++s) {
-        Slot &sl = b->slots[s];
-        sl.hl = horizontal_lanes_valid(sl.Dpad, b->tuning.horizontal_lanes) ? b->tuning.horizontal_lanes
-                                                                              : horizontal_lanes(sl.Dpad);
-        AggregateArgs &a = agg[s];
-        a = AggregateArgs{};
-        a.census_l = b->scratch + sl.off_census_l;
-        a.census_r = b->scratch + sl.off_census_r;
-        a.W = sl.p.width; a.H = sl.p.height; a.D = sl.p.max_disp; a.Dpad = sl.Dpad; a.bits = sl.bits;
-        a.p1 = sl.p.p1; a.p2 = sl.p.p2; a.ndirs = sl.ndirs;
-        a.block_begin[0] = 0;
-        auto &lst = groups[{sl.Dpad, sl.wide}];
-        for (int r = 0; r < sl.ndirs; ++r) {
-            a.dx[r] = kPathDx[r];
-            a.dy[r] = kPathDy[r];
-            a.out[r] = b->scratch + sl.off_paths[r];
-            const int nb = aggregate_blocks(kPathDx[r], kPathDy[r], a.W, a.H, sl.hl);
-            for (int k = 0; k < nb; ++k) {
-                const int work = aggregate_block_work(kPathDx[r], kPathDy[r], k, a.W, a.H, sl.hl, sl.Dpad);
-                lst.push_back({work, ((uint32_t)s << 20) | (uint32_t)(a.block_begin[r] + k)});
-            }
-            a.block_begin[r + 1] = a.block_begin[r] + nb;
-        }
-    }
-    int counter = 0;
-    for (auto &kv : groups) {
-        auto &lst = kv.second;
-        std::stable_sort(lst.begin(), lst.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
-        // the group's blocks run in one launch: its largest block sets the scale
-        // of every slot's issue priorities
-        const int gmax = lst.empty() ? 0 : lst.front().first;
-        for (auto &e : lst) agg[e.second >> 20].max_item_work = gmax;
-        simsense_batch::AggGroup gr{};
-        gr.dpad = kv.first.first;
-        gr.wide = kv.first.second;
-        gr.hl = horizontal_lanes_valid(gr.dpad, b->tuning.horizontal_lanes) ? b->tuning.horizontal_lanes
-                                                                            : horizontal_lanes(gr.dpad);
-        gr.item_off = items.size();
-        gr.nitems = (int)lst.size();
-        gr.counter = counter++;
-        for (auto &e : lst) items.push_back(e.second);
-        b->agg_groups.push_back(gr);
-    }
-    // selection: group by (Dpad, ndirs, small)
     std::vector<SelectArgs> sel(n);
-    std::map<std::tuple<int, int, bool>, std::vector<uint32_t>> sgroups;
-    for (int s = 0; s < n; ++s) {
-        const Slot &sl = b->slots[s];
-        SelectArgs &a = sel[s];
-        a = SelectArgs{};
-        for (int r = 0; r < sl.ndirs; ++r) a.paths[r] = b->scratch + sl.off_paths[r];
-        a.ndirs = sl.ndirs;
-        a.W = sl.p.width; a.H = sl.p.height; a.D = sl.p.max_disp; a.Dpad = sl.Dpad;
-        a.uniqueness_pct = sl.p.uniqueness_pct; a.lr_max_diff = sl.p.lr_max_diff; a.subpixel = sl.p.subpixel;
-        a.small_values = sl.bits + sl.p.p2 <= 127;
-        a.disp_int = b->scratch + sl.off_dint;
-        a.cost_best = (uint16_t *)(b->scratch + sl.off_s1);
-        a.cost_second = (uint16_t *)(b->scratch + sl.off_s2);
-        a.disp_right = b->scratch + sl.off_dright;
-        a.disp_sub = (float *)(b->scratch + sl.off_dsub);
-        a.masked = (float *)(b->scratch + sl.off_masked);
-        a.flags = b->scratch + sl.off_flags;
-        auto &lst = sgroups[{sl.Dpad, sl.ndirs, a.small_values != 0}];
-        for (int y = 0; y < sl.p.height; ++y) lst.push_back(((uint32_t)s << 20) | (uint32_t)y);
-    }
-    for (auto &kv : sgroups) {
-        simsense_batch::SelGroup gr{};
-        gr.dpad = std::get<0>(kv.first);
-        gr.ndirs = std::get<1>(kv.first);
-        gr.small = std::get<2>(kv.first);
-        gr.item_off = items.size();
-        gr.nitems = (int)kv.second.size();
-        items.insert(items.end(), kv.second.begin(), kv.second.end());
-        b->sel_groups.push_back(gr);
-    }
-    // post
-    b->post_item_off = items.size();
-    for (int s = 0; s < n; ++s) {
-        const Slot &sl = b->slots[s];
-        const int t = ((sl.p.width + 63) / 64) * ((sl.p.height + 3) / 4);
-        for (int i = 0; i < t; ++i) items.push_back(((uint32_t)s << 20) | (uint32_t)i);
-    }
-    b->post_nitems = (int)(items.size() - b->post_item_off);
+    int counter = 0;
+    b->lphases.clear();
+    auto add_phase = [&](int s0, int s1, std::vector<simsense_batch::Phase> &dest) {
+        simsense_batch::Phase P{};
+        P.s0 = s0;
+        P.s1 = s1;
+        // census: every image of the phase
+        P.census_item_off = items.size();
+        for (int s = P.s0; s < P.s1; ++s) {
+            const Slot &sl = b->slots[s];
+            const int t = census_tiles(sl.p.width, sl.p.height);
+            for (int img = 0; img < 2; ++img)
+                for (int i = 0; i < t; ++i) items.push_back(((uint32_t)(2 * s + img) << 20) | (uint32_t)i);
+        }
+        P.census_nitems = (int)(items.size() - P.census_item_off);
+        // aggregation: group slots by (Dpad, wide); items largest estimated work first
+        std::map<std::pair<int, bool>, std::vector<std::pair<int, uint32_t>>> groups;
+        for (int s = P.s0; s < P.s1; ++s) {
+            Slot &sl = b->slots[s];
+            sl.hl = horizontal_lanes_valid(sl.Dpad, b->tuning.horizontal_lanes) ? b->tuning.horizontal_lanes
+                                                                                  : horizontal_lanes(sl.Dpad);
+            AggregateArgs &a = agg[s];
+            const int scale = a.max_item_work;  // set by an earlier plan, if any
+            a = AggregateArgs{};
+            a.max_item_work = scale;
+            a.census_l = b->scratch + sl.off_census_l;
+            a.census_r = b->scratch + sl.off_census_r;
+            a.W = sl.p.width; a.H = sl.p.height; a.D = sl.p.max_disp; a.Dpad = sl.Dpad; a.bits = sl.bits;
+            a.p1 = sl.p.p1; a.p2 = sl.p.p2; a.ndirs = sl.ndirs;
+            a.block_begin[0] = 0;
+            auto &lst = groups[{sl.Dpad, sl.wide}];
+            for (int r = 0; r < sl.ndirs; ++r) {
+                a.dx[r] = kPathDx[r];
+                a.dy[r] = kPathDy[r];
+                a.out[r] = b->scratch + sl.off_paths[r];
+                const int nb = aggregate_blocks(kPathDx[r], kPathDy[r], a.W, a.H, sl.hl);
+                for (int k = 0; k < nb; ++k) {
+                    const int work = aggregate_block_work(kPathDx[r], kPathDy[r], k, a.W, a.H, sl.hl, sl.Dpad);
+                    lst.push_back({work, ((uint32_t)s << 20) | (uint32_t)(a.block_begin[r] + k)});
+                }
+                a.block_begin[r + 1] = a.block_begin[r] + nb;
+            }
+        }
+        P.agg0 = (int)b->agg_groups.size();
+        for (auto &kv : groups) {
+            auto &lst = kv.second;
+            std::stable_sort(lst.begin(), lst.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
+            // the group's blocks run in one launch: its largest block sets the scale
+            // of every slot's issue priorities
+            const int gmax = lst.empty() ? 0 : lst.front().first;
+            // (the plain form's phases set the scale; slots of equal size get the
+            // same one in every plan)
+            if (&dest == &b->phases)
+                for (auto &e : lst) agg[e.second >> 20].max_item_work = gmax;
+            simsense_batch::AggGroup gr{};
+            gr.dpad = kv.first.first;
+            gr.wide = kv.first.second;
+            gr.hl = horizontal_lanes_valid(gr.dpad, b->tuning.horizontal_lanes) ? b->tuning.horizontal_lanes
+                                                                                : horizontal_lanes(gr.dpad);
+            gr.item_off = items.size();
+            gr.nitems = (int)lst.size();
+            gr.counter = counter++;
+            for (auto &e : lst) items.push_back(e.second);
+            b->agg_groups.push_back(gr);
+        }
+        P.nagg = (int)b->agg_groups.size() - P.agg0;
+        // selection: group by (Dpad, ndirs, small)
+        std::map<std::tuple<int, int, bool>, std::vector<uint32_t>> sgroups;
+        for (int s = P.s0; s < P.s1; ++s) {
+            const Slot &sl = b->slots[s];
+            SelectArgs &a = sel[s];
+            a = SelectArgs{};
+            for (int r = 0; r < sl.ndirs; ++r) a.paths[r] = b->scratch + sl.off_paths[r];
+            a.ndirs = sl.ndirs;
+            a.W = sl.p.width; a.H = sl.p.height; a.D = sl.p.max_disp; a.Dpad = sl.Dpad;
+            a.uniqueness_pct = sl.p.uniqueness_pct; a.lr_max_diff = sl.p.lr_max_diff; a.subpixel = sl.p.subpixel;
+            a.small_values = sl.bits + sl.p.p2 <= 127;
+            a.disp_int = b->scratch + sl.off_dint;
+            a.cost_best = (uint16_t *)(b->scratch + sl.off_s1);
+            a.cost_second = (uint16_t *)(b->scratch + sl.off_s2);
+            a.disp_right = b->scratch + sl.off_dright;
+            a.disp_sub = (float *)(b->scratch + sl.off_dsub);
+            a.masked = (float *)(b->scratch + sl.off_masked);
+            a.flags = b->scratch + sl.off_flags;
+            auto &lst = sgroups[{sl.Dpad, sl.ndirs, a.small_values != 0}];
+            for (int y = 0; y < sl.p.height; ++y) lst.push_back(((uint32_t)s << 20) | (uint32_t)y);
+        }
+        P.sel0 = (int)b->sel_groups.size();
+        for (auto &kv : sgroups) {
+            simsense_batch::SelGroup gr{};
+            gr.dpad = std::get<0>(kv.first);
+            gr.ndirs = std::get<1>(kv.first);
+            gr.small = std::get<2>(kv.first);
+            gr.item_off = items.size();
+            gr.nitems = (int)kv.second.size();
+            items.insert(items.end(), kv.second.begin(), kv.second.end());
+            b->sel_groups.push_back(gr);
+        }
+        P.nsel = (int)b->sel_groups.size() - P.sel0;
+        // post
+        P.post_item_off = items.size();
+        for (int s = P.s0; s < P.s1; ++s) {
+            const Slot &sl = b->slots[s];
+            const int t = ((sl.p.width + 63) / 64) * ((sl.p.height + 3) / 4);
+            for (int i = 0; i < t; ++i) items.push_back(((uint32_t)s << 20) | (uint32_t)i);
+        }
+        P.post_nitems = (int)(items.size() - P.post_item_off);
+        dest.push_back(P);
+    };
+    const int nph = batch_phases(n);
+    for (int ph = 0; ph < nph; ++ph)
+        add_phase((int)((int64_t)n * ph / nph), (int)((int64_t)n * (ph + 1) / nph), b->phases);
+    add_phase(0, n, b->lphases);
+    if (counter > 64) return SIMSENSE_ERR_UNSUPPORTED;  // the work-queue counters one batch holds
     b->census_wide = b->slots[0].wide;
 
     if (b->d_items) (void)hipFree(b->d_items);
@@ -210,20 +256,25 @@ __global__ void zero_words(unsigned *c, int n)
     for (int i = threadIdx.x; i < n; i += blockDim.x) c[i] = 0u;
 }
 
-// census, aggregation and selection of every slot
-int enqueue_match_batch(simsense_batch *b, hipStream_t s, bool need_right = true)
+// census of one phase's images (the launch also clears its work-queue counters)
+int enqueue_census_phase(simsense_batch *b, const simsense_batch::Phase &P, hipStream_t s)
 {
-    const int ngroups = (int)b->agg_groups.size();
     CensusBatch cb{};
-    cb.zero = b->d_counters;  // the census launch clears the work-queue counters
-    cb.nzero = ngroups;
+    cb.zero = P.nagg > 0 ? b->d_counters + b->agg_groups[P.agg0].counter : nullptr;
+    cb.nzero = P.nagg;
     cb.jobs = b->d_cjobs;
-    cb.items = b->d_items + b->census_item_off;
-    cb.nitems = b->census_nitems;
+    cb.items = b->d_items + P.census_item_off;
+    cb.nitems = P.census_nitems;
     cb.max_cw = b->max_cw;
     cb.max_ch = b->max_ch;
     B_TRY(launch_census_batch(cb, b->census_wide, s));
-    for (const auto &g : b->agg_groups) {
+    return SIMSENSE_OK;
+}
+
+int enqueue_aggregate_phase(simsense_batch *b, const simsense_batch::Phase &P, hipStream_t s)
+{
+    for (int i = P.agg0; i < P.agg0 + P.nagg; ++i) {
+        const auto &g = b->agg_groups[i];
         AggregateQueue q{};
         q.slots = b->d_agg;
         q.items = b->d_items + g.item_off;
@@ -232,7 +283,13 @@ int enqueue_match_batch(simsense_batch *b, hipStream_t s, bool need_right = true
         const int grid = std::min(g.nitems, std::max(1, b->tuning.blocks_per_cu) * b->num_cus);
         B_TRY(launch_aggregate_queue(q, g.dpad, g.wide, g.hl, grid, s));
     }
-    for (const auto &g : b->sel_groups) {
+    return SIMSENSE_OK;
+}
+
+int enqueue_select_phase(simsense_batch *b, const simsense_batch::Phase &P, hipStream_t s, bool need_right)
+{
+    for (int i = P.sel0; i < P.sel0 + P.nsel; ++i) {
+        const auto &g = b->sel_groups[i];
         SelectBatch sb{};
         sb.slots = b->d_sel;
         sb.items = b->d_items + g.item_off;
@@ -244,86 +301,104 @@ int enqueue_match_batch(simsense_batch *b, hipStream_t s, bool need_right = true
     return SIMSENSE_OK;
 }
 
-int enqueue_post_batch(simsense_batch *b, hipStream_t s)
+int enqueue_post_phase(simsense_batch *b, const simsense_batch::Phase &P, hipStream_t s)
 {
     PostBatch pb{};
     pb.slots = b->d_post;
-    pb.items = b->d_items + b->post_item_off;
-    pb.nitems = b->post_nitems;
+    pb.items = b->d_items + P.post_item_off;
+    pb.nitems = P.post_nitems;
     B_TRY(launch_post_batch(pb, s));
     return SIMSENSE_OK;
 }
 
-// the plain pass sequence, as captured into the graph
-int enqueue_batch(simsense_batch *b, hipStream_t s)
+// the fused net over one phase's slots: one launch for a run of slots whose
+// buffers lie at equal distances (equal-sized slots do), else per slot
+int enqueue_net_phase(simsense_batch *b, const simsense_batch::Phase &P, simsense_net *net, float tau, unsigned *uncertain,
+                      hipStream_t s)
 {
-    const int rc = enqueue_match_batch(b, s);
-    return rc != SIMSENSE_OK ? rc : enqueue_post_batch(b, s);
+    const int c0 = P.s0, cn = P.s1 - P.s0;
+    if (cn <= 0) return SIMSENSE_OK;
+    const Slot &s0 = b->slots[c0];
+    const int W = s0.p.width, H = s0.p.height;
+    auto gap = [&](size_t Slot::*off, int k) {
+        return (int64_t)(b->slots[c0 + k].*off) - (int64_t)(b->slots[c0 + k - 1].*off);
+    };
+    bool uniform = true;
+    for (int k = 2; k < cn && uniform; ++k)
+        uniform = gap(&Slot::off_dsub, k) == gap(&Slot::off_dsub, 1) &&
+                  gap(&Slot::off_masked, k) == gap(&Slot::off_masked, 1) &&
+                  gap(&Slot::off_flags, k) == gap(&Slot::off_flags, 1);
+    // the net reads S1, S2 and d* of image i at one byte distance per image
+    for (int k = 1; k < cn && uniform; ++k)
+        uniform = gap(&Slot::off_s1, k) == gap(&Slot::off_s1, 1) && gap(&Slot::off_s2, k) == gap(&Slot::off_s1, 1) &&
+                  gap(&Slot::off_dint, k) == gap(&Slot::off_s1, 1);
+    const int per = uniform ? cn : 1;
+    for (int k = 0; k < cn; k += per) {
+        const Slot &sl = b->slots[c0 + k];
+        // the features are built inside the net from the selection outputs
+        net::InferArgs ia = net::infer_args(net, nullptr, per, H, W);
+        ia.ir_jobs = b->d_cjobs + 2 * (c0 + k);  // the left images, as refreshed per call
+        ia.s1 = (const uint16_t *)(b->scratch + sl.off_s1);
+        ia.s2 = (const uint16_t *)(b->scratch + sl.off_s2);
+        ia.dint = b->scratch + sl.off_dint;
+        ia.sel_stride = per > 1 ? gap(&Slot::off_s1, 1) : 0;
+        ia.max_disp = sl.p.max_disp;
+        ia.smax = (float)(sl.ndirs * (sl.bits + sl.p.p2));
+        ia.d2_sub = (const float *)(b->scratch + sl.off_dsub);
+        ia.masked = (float *)(b->scratch + sl.off_masked);
+        ia.flags = b->scratch + sl.off_flags;
+        if (per > 1) {
+            ia.d2_stride = gap(&Slot::off_dsub, 1) / 4;
+            ia.masked_stride = gap(&Slot::off_masked, 1) / 4;
+            ia.flags_stride = gap(&Slot::off_flags, 1);
+        }
+        ia.uncertain = uncertain + c0 + k;
+        ia.tau = tau;
+        B_TRY(net::launch_infer(ia, s));
+    }
+    return SIMSENSE_OK;
 }
 
-// the learned pass sequence: matching, then the fused net (which builds its
-// input features from the selection outputs) and the combination with the
-// per-slot uncertainty count, one launch over all slots, then post
-int enqueue_learned_batch(simsense_batch *b, simsense_net *net, float tau, unsigned *uncertain, hipStream_t s)
+// The pass sequence of every phase: phase p on stream (p even: s, odd: the side
+// stream), its aggregation after phase p - 1's, and the side stream joined back
+// into s at the end.  With a net, the learned form: matching without the right
+// disparities, then the fused net (features built from the selection outputs, the
+// per-slot uncertainty counts), then median and depth.
+int enqueue_phases(simsense_batch *b, hipStream_t s, simsense_net *net, float tau, unsigned *uncertain)
 {
-    hipLaunchKernelGGL(zero_words, dim3(1), dim3(256), 0, s, uncertain, b->n);
-    B_TRY(hipGetLastError());
-    // the learned form reads d*, S1, S2 and the sub-pixel disparity only
-    int rc = enqueue_match_batch(b, s, /*need_right=*/false);
-    if (rc != SIMSENSE_OK) return rc;
-    const Slot &s0 = b->slots[0];
-    const int W = s0.p.width, H = s0.p.height;
-    const int64_t P = (int64_t)W * H;
-    const int chunk = b->n;  // the features are never stored: no buffer bounds the chunk
-    for (int c0 = 0; c0 < b->n; c0 += chunk) {
-        const int cn = std::min(chunk, b->n - c0);
-        // the fused net + combination, one launch for the chunk when its slots'
-        // buffers lie at equal distances (equal-sized slots do), else per slot
-        auto gap = [&](size_t Slot::*off, int k) {
-            return (int64_t)(b->slots[c0 + k].*off) - (int64_t)(b->slots[c0 + k - 1].*off);
-        };
-        bool uniform = true;
-        for (int k = 2; k < cn && uniform; ++k)
-            uniform = gap(&Slot::off_dsub, k) == gap(&Slot::off_dsub, 1) &&
-                      gap(&Slot::off_masked, k) == gap(&Slot::off_masked, 1) &&
-                      gap(&Slot::off_flags, k) == gap(&Slot::off_flags, 1);
-        // the net reads S1, S2 and d* of image i at one byte distance per image
-        for (int k = 1; k < cn && uniform; ++k)
-            uniform = gap(&Slot::off_s1, k) == gap(&Slot::off_s1, 1) && gap(&Slot::off_s2, k) == gap(&Slot::off_s1, 1) &&
-                      gap(&Slot::off_dint, k) == gap(&Slot::off_s1, 1);
-        const int per = uniform ? cn : 1;
-        for (int k = 0; k < cn; k += per) {
-            const Slot &sl = b->slots[c0 + k];
-            // the features are built inside the net from the selection outputs
-            net::InferArgs ia = net::infer_args(net, nullptr, per, H, W);
-            ia.ir_jobs = b->d_cjobs + 2 * (c0 + k);  // the left images, as refreshed per call
-            ia.s1 = (const uint16_t *)(b->scratch + sl.off_s1);
-            ia.s2 = (const uint16_t *)(b->scratch + sl.off_s2);
-            ia.dint = b->scratch + sl.off_dint;
-            ia.sel_stride = per > 1 ? gap(&Slot::off_s1, 1) : 0;
-            ia.max_disp = sl.p.max_disp;
-            ia.smax = (float)(sl.ndirs * (sl.bits + sl.p.p2));
-            ia.d2_sub = (const float *)(b->scratch + sl.off_dsub);
-            ia.masked = (float *)(b->scratch + sl.off_masked);
-            ia.flags = b->scratch + sl.off_flags;
-            if (per > 1) {
-                ia.d2_stride = gap(&Slot::off_dsub, 1) / 4;
-                ia.masked_stride = gap(&Slot::off_masked, 1) / 4;
-                ia.flags_stride = gap(&Slot::off_flags, 1);
-            }
-            ia.uncertain = uncertain + c0 + k;
-            ia.tau = tau;
-            B_TRY(net::launch_infer(ia, s));
-        }
+    const std::vector<simsense_batch::Phase> &phases = net ? b->lphases : b->phases;
+    const int nph = (int)phases.size();
+    if (net) {
+        hipLaunchKernelGGL(zero_words, dim3(1), dim3(256), 0, s, uncertain, b->n);
+        B_TRY(hipGetLastError());
     }
-    return enqueue_post_batch(b, s);
+    if (nph > 1) {
+        B_TRY(hipEventRecord(b->ev_fork, s));
+        B_TRY(hipStreamWaitEvent(b->side_stream, b->ev_fork, 0));
+    }
+    int rc = SIMSENSE_OK;
+    for (int ph = 0; ph < nph && rc == SIMSENSE_OK; ++ph) {
+        hipStream_t st = ph % 2 == 0 ? s : b->side_stream;
+        rc = enqueue_census_phase(b, phases[ph], st);
+        if (rc == SIMSENSE_OK && ph > 0) B_TRY(hipStreamWaitEvent(st, b->ev_agg[ph - 1], 0));
+        if (rc == SIMSENSE_OK) rc = enqueue_aggregate_phase(b, phases[ph], st);
+        if (rc == SIMSENSE_OK && ph + 1 < nph) B_TRY(hipEventRecord(b->ev_agg[ph], st));
+        if (rc == SIMSENSE_OK) rc = enqueue_select_phase(b, phases[ph], st, /*need_right=*/!net);
+        if (rc == SIMSENSE_OK && net) rc = enqueue_net_phase(b, phases[ph], net, tau, uncertain, st);
+        if (rc == SIMSENSE_OK) rc = enqueue_post_phase(b, phases[ph], st);
+    }
+    if (nph > 1) {
+        B_TRY(hipEventRecord(b->ev_join, b->side_stream));
+        B_TRY(hipStreamWaitEvent(s, b->ev_join, 0));
+    }
+    return rc;
 }
 
 int capture_graph(simsense_batch *b, hipGraphExec_t *exec, simsense_net *net, float tau, unsigned *uncertain)
 {
     hipGraph_t graph;
     B_TRY(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal));
-    int rc = net ? enqueue_learned_batch(b, net, tau, uncertain, b->capture_stream) : enqueue_batch(b, b->capture_stream);
+    int rc = enqueue_phases(b, b->capture_stream, net, tau, uncertain);
     hipError_t e = hipStreamEndCapture(b->capture_stream, &graph);
     if (rc != SIMSENSE_OK) return rc;
     B_TRY(e);
@@ -405,6 +480,11 @@ void free_batch(simsense_batch *b)
 {
     drop_graphs(b);
     if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+    if (b->side_stream) (void)hipStreamDestroy(b->side_stream);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+    for (int i = 0; i < kBatchPhases; ++i)
+        if (b->ev_agg[i]) (void)hipEventDestroy(b->ev_agg[i]);
     for (int i = 0; i < 2; ++i) {
         if (b->staged[i]) (void)hipEventDestroy(b->staged[i]);
         if (b->h_cjobs[i]) (void)hipHostFree(b->h_cjobs[i]);
@@ -484,8 +564,14 @@ int simsense_batch_create(const simsense_params *params, int32_t n, simsense_bat
     }
     if (rc == SIMSENSE_OK && hipHostMalloc((void **)&b->h_uncertain, n * sizeof(unsigned), 0) != hipSuccess)
         rc = SIMSENSE_ERR_OUT_OF_MEMORY;
-    if (rc == SIMSENSE_OK && hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking) != hipSuccess)
+    if (rc == SIMSENSE_OK && (hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking) != hipSuccess ||
+                              hipStreamCreateWithFlags(&b->side_stream, hipStreamNonBlocking) != hipSuccess))
         rc = SIMSENSE_ERR_DEVICE;
+    if (rc == SIMSENSE_OK && (hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess ||
+                              hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming) != hipSuccess))
+        rc = SIMSENSE_ERR_DEVICE;
+    for (int i = 0; i < kBatchPhases && rc == SIMSENSE_OK; ++i)
+        if (hipEventCreateWithFlags(&b->ev_agg[i], hipEventDisableTiming) != hipSuccess) rc = SIMSENSE_ERR_DEVICE;
     if (rc == SIMSENSE_OK) rc = build_plan(b);
     if (rc != SIMSENSE_OK) {
         (void)hipGetLastError();
