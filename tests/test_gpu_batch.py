@@ -137,3 +137,33 @@ def test_learned_batch_matches_single_pair_learned_path(orc, nat):
     b.close()
     ss.close()
     net.close()
+
+
+@pytest.mark.parametrize("n", [1, 2, 7])
+def test_batch_phases_match_single_pairs(orc, nat, n):
+    """The plain form runs as up to 4 phases of consecutive slots on two streams
+    (1, 2 and 7 slots give 1, 2 and 4 phases of uneven sizes): every pair equals
+    its single-pair result, on two replays of the graph."""
+    import torch
+    shapes = [(160, 90, 64), (97, 61, 37), (200, 50, 96)] * 3
+    params, lefts, rights = make_batch_inputs(orc, shapes[:n], seed0=500)
+    L = [dev(a) for a in lefts]
+    R = [dev(a) for a in rights]
+    singles = []
+    for p, l, r in zip(params, L, R):
+        ss = nat.SimSense(p)
+        singles.append([t.cpu().numpy() for t in ss(l, r)])
+        ss.close()
+    b = nat.Batch(params)
+    outs = b.outputs()
+    for rep in range(2):
+        for o in outs:
+            for t in o.values():
+                t.fill_(0)
+        b.compute(L, R, outs)
+        torch.cuda.synchronize()
+        for i, (o, s) in enumerate(zip(outs, singles)):
+            assert np.array_equal(o["depth"].cpu().numpy(), s[0]), (rep, i)
+            assert np.array_equal(o["disp"].cpu().numpy(), s[1]), (rep, i)
+            assert np.array_equal(o["flags"].cpu().numpy(), s[2]), (rep, i)
+    b.close()
