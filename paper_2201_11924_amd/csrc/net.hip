@@ -58,7 +58,11 @@ __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v)
 // as in memory; positions outside the image are zeros), so every input pixel is
 // loaded once per sub-strip instead of once per tap, and a B fragment (8
 // channels of one pixel and tap) is one aligned 16-byte LDS read.  Each output's
-// products are summed onto its starting value in k order.
+// products are summed onto its starting value in k order.  A 32-channel ReLU layer
+// also stores which of its stored outputs are > 0, packed 4 bytes per pixel: byte q
+// holds channels 4q .. 4q+3 (bits 0-3) and 16+4q .. 16+4q+3 (bits 4-7), the eight
+// channels lane quad q holds in the MFMA output layout; backward-data reads that
+// byte instead of the 64-byte activation.
 constexpr int kConvCols = 64;   // output columns per block
 constexpr int kConvRows = 4;    // output rows per sub-strip (one per wave)
 constexpr int kConvSubs = 4;    // sub-strips per block
@@ -129,18 +133,15 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a)
         if (y0 >= H) break;
         __syncthreads();  // the previous sub-strip's reads of the stage are done
         const int y = y0 + wave;  // this wave's output row
-        // the masked epilogue's forward activations of this wave's four tiles,
-        // loaded while the stage is filled
-        uint2 mk[kConvCols / 16][MB];
+        // the masked epilogue's ReLU masks of this wave's four tiles (one byte per
+        // lane: the lane's 8 output channels), loaded while the stage is filled
+        uint32_t mk[kConvCols / 16];
 #pragma unroll
-        for (int t = 0; t < kConvCols / 16; ++t)
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb) {
-                mk[t][mb] = make_uint2(0, 0);
-                const int x = x0 + 16 * t + col;
-                if (EPI == EPI_MASK && y < H && x < W)
-                    mk[t][mb] = *(const uint2 *)(a.mask + (img + (int64_t)y * W + x) * COUTP + 16 * mb + 4 * quad);
-            }
+        for (int t = 0; t < kConvCols / 16; ++t) {
+            mk[t] = 0;
+            const int x = x0 + 16 * t + col;
+            if (EPI == EPI_MASK && y < H && x < W) mk[t] = a.mask[(img + (int64_t)y * W + x) * 4 + quad];
+        }
         for (int e = threadIdx.x; e < NCH; e += 256) {
             const int ch = 8 * (e % XC), pxi = e / XC, c = pxi % SC, r = pxi / SC;
             const int gy = y0 - 1 + r, gx = x0 - 1 + c;
@@ -176,6 +177,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a)
                     acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[mb][c], bv, acc[mb], 0, 0, 0);
             }
             if (x >= W) continue;
+            uint32_t mbits = 0;
             // D layout: lane holds rows (output channels) 4*quad .. +3 of column (pixel) col
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb) {
@@ -187,26 +189,29 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a)
                         o[1] = acc[mb][1];
                     }
                 } else {
-                    const uint2 mw = mk[t][mb];
-                    const uint16_t m4[4] = {(uint16_t)mw.x, (uint16_t)(mw.x >> 16), (uint16_t)mw.y, (uint16_t)(mw.y >> 16)};
                     float h[4];
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         float v = acc[mb][i];
-                        if (EPI == EPI_RELU) {
-                            v = relu(v);
-                        } else {
-                            const uint16_t m = m4[i];
-                            v = (m & 0x7FFF) != 0 && !(m & 0x8000) ? v : 0.0f;  // mask > 0
-                        }
+                        if (EPI == EPI_RELU) v = relu(v);
+                        else v = (mk[t] >> (4 * mb + i)) & 1u ? v : 0.0f;  // the forward output was > 0
                         h[i] = v;
                     }
                     uint2 w;
                     w.x = pack_bf16(h[0], h[1]);
                     w.y = pack_bf16(h[2], h[3]);
                     *(uint2 *)((uint16_t *)a.out + p * COUTP + co) = w;
+                    if (EPI == EPI_RELU && COUTP == 32) {
+                        // which of the stored values are > 0 (non-zero magnitude, sign
+                        // clear), as bits 4 mb + i of the lane's mask byte
+                        const uint32_t q[4] = {w.x & 0xFFFFu, w.x >> 16, w.y & 0xFFFFu, w.y >> 16};
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            mbits |= ((q[i] & 0x7FFFu) != 0 && !(q[i] & 0x8000u) ? 1u : 0u) << (4 * mb + i);
+                    }
                 }
             }
+            if (EPI == EPI_RELU && COUTP == 32 && a.mask_out) a.mask_out[p * 4 + quad] = (uint8_t)mbits;
         }
     }
 }

@@ -95,6 +95,7 @@ int ss::net::enqueue_forward(simsense_net *n, const uint16_t *x0, int batch, int
     const uint16_t *in = x0;
     for (int l = 0; l < 3; ++l) {
         c.in = in; c.weights = n->wf[l]; c.bias = n->bias[l]; c.mask = nullptr; c.out = n->act[l];
+        c.mask_out = n->relu_mask[l];
         NET_TRY(launch_conv(c, kLayers[l].cinp, kLayers[l].coutp, EPI_RELU, s));
         in = n->act[l];
     }
@@ -141,7 +142,7 @@ int simsense_net_create(int64_t max_pixels, uint64_t seed, simsense_net **out)
     n->max_pixels = max_pixels;
     const size_t P = (size_t)max_pixels;
     const int wblocks = kMaxWgradBlocks;
-    size_t sz[32];
+    size_t sz[48];
     int k = 0;
     for (int i = 0; i < 4; ++i) sz[k++] = a256(kNumParams * sizeof(float));          // params, m, v, grad
     for (int l = 0; l < 4; ++l) sz[k++] = a256(kLayers[l].coutp * kpad(kLayers[l].cinp) * 2);  // wf
@@ -159,6 +160,8 @@ int simsense_net_create(int64_t max_pixels, uint64_t seed, simsense_net **out)
     sz[k++] = a256(3 * sizeof(float));                              // loss
     sz[k++] = a256(P * 4);           // t_res
     sz[k++] = a256(P);               // t_valid
+    for (int l = 0; l < 3; ++l) sz[k++] = a256(P * 4);  // relu_mask
+    static_assert(sizeof(sz) / sizeof(sz[0]) >= 4 + 4 + 4 + 4 + 1 + 3 + 1 + 1 + 3 + 5 + 2 + 3, "one size per buffer");
     size_t total = 0;
     for (int i = 0; i < k; ++i) total += sz[i];
     if (hipMalloc(&n->block, total) != hipSuccess) {
@@ -185,6 +188,7 @@ int simsense_net_create(int64_t max_pixels, uint64_t seed, simsense_net **out)
     n->loss = (float *)take();
     n->t_res = (float *)take();
     n->t_valid = (uint8_t *)take();
+    for (int l = 0; l < 3; ++l) n->relu_mask[l] = (uint8_t *)take();
     n->last_stream = nullptr;
     n->step = 0;
     n->last_P = 0;
@@ -345,7 +349,7 @@ int simsense_net_train_step(simsense_net *n, const uint16_t *features, const flo
         if (l > 0) {
             // gradient at the previous layer's output: backward-data conv, masked by its ReLU
             ConvArgs c{};
-            c.in = dy; c.weights = n->wb[l]; c.bias = nullptr; c.mask = xin[l]; c.out = n->g[l - 1];
+            c.in = dy; c.weights = n->wb[l]; c.bias = nullptr; c.mask = n->relu_mask[l - 1]; c.out = n->g[l - 1];
             c.batch = batch; c.H = height; c.W = width;
             NET_TRY(launch_conv(c, kLayers[l].coutp, kLayers[l].cinp, EPI_MASK, s));
             dy = n->g[l - 1];

@@ -20,7 +20,8 @@ struct ConvArgs {
     const uint16_t *in;       // bf16 NHWC, CINP channels
     const uint16_t *weights;  // bf16 [COUTP][kpad(CINP)]
     const float *bias;        // fp32 [COUTP] or null
-    const uint16_t *mask;     // bf16 NHWC, COUTP channels (backward-data only)
+    const uint8_t *mask;      // backward-data: the ReLU masks of its output channels, packed as below
+    uint8_t *mask_out;        // ReLU layers (or null): their outputs' masks, packed; 32 channels only
     void *out;                // bf16 NHWC COUTP channels, or fp32 [P][2] for the linear layer
     int batch, H, W;
 };
@@ -158,6 +159,7 @@ struct simsense_net {
     float *out;            // [P][2]
     uint16_t *dy4;         // [P][16]
     uint16_t *g[3];        // [P][32] gradient at the output of layer l (ReLU-masked), l = 0..2
+    uint8_t *relu_mask[3]; // [P][4] which outputs of layers 1..3 are > 0, packed (see conv3x3_kernel)
     int64_t last_P;        // pixels of the last forward or training call
     float *wpart, *bpart;  // weight / bias gradient partials
     float *lpart, *scal, *loss;
