@@ -37,11 +37,12 @@ struct Slot {
 size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // phases the plain form of a batch of n slots is split into (consecutive slots, as
-// equal in number as can be; one phase for a single slot).  Measured at 64 and 256
-// sensor pairs: 4 phases 5% more pairs/s than 1 for the plain form; the learned
-// form, whose fused-net blocks need a whole unit, runs as one phase (4 phases: 4%
-// fewer pairs/s).
-constexpr int kBatchPhases = 4;
+// equal in number as can be; one phase for a single slot).  Measured on 256 sensor
+// pairs in 64-pair batches: 2271 pairs/s with 1 phase, 2392 with 4, 2453 with 8; at
+// most 7 padded-disparity groups per phase keep 8 phases within the 64 work-queue
+// counters.  The learned form, whose fused-net blocks need a whole unit, runs as
+// one phase (4 phases: 4% fewer pairs/s).
+constexpr int kBatchPhases = 8;
 int batch_phases(int n) { return std::min(n, kBatchPhases); }
 
 }  // namespace
